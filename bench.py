@@ -1,0 +1,351 @@
+#!/usr/bin/env python
+"""Benchmark of the MI355X weighted sort-means color quantizer.
+
+Metric: WSM color-iterations/s (unique colors x iterations per second of the
+whole pipeline) and images/s, on the 512x512 synthetic photo-like workload
+(seeded sum of 6 sinusoidal color fields + N(0, 6^2) noise, ~180k unique
+colors) quantized at K = 16, 64 and 256 (WSM-C: eps = 1e-4, at most 50
+iterations), compared with full-search batch k-means on the GPU from the same
+initial palette (same trajectory, so equal MSE by construction; checked).
+
+One step = one pass of the whole hot path over the image: unique-color
+reduction, then for each K: initial palette from the seeded random subset,
+state init, iterations, pixel map (with MSE).  Inputs are resident in HBM
+before the timed region.
+
+Prints ONE JSON line.  Extra objects: per-K details, the full-search
+comparators, the roofline of the dominant kernel (measured live with HIP
+events around each of its launches, in a separate pass over the same
+workload), the reduction/map rooflines on the 4096x4096 workload, and the
+FP64 CPU oracle timed on this host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+EPS = 1e-4
+MAX_ITERS = 50
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target CPU time of the oracle baseline sample")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of "
+                                   "it (see DESIGN.md for how the path would shard)",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1011_0093_amd as wsm
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    img_np = synth.workload_image("medium", args.seed)
+    H, W, _ = img_np.shape
+    N = H * W
+    Ks = list(synth.WORKLOADS["medium"]["ks"])
+    img = torch.from_numpy(img_np).to(dev)
+    cap = min(N, 1 << 24)
+    colors = torch.empty(cap, dtype=torch.int32, device=dev)
+    counts = torch.empty(cap, dtype=torch.int32, device=dev)
+    nu = torch.empty(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(wsm.reduce_workspace_bytes(N), dtype=torch.uint8, device=dev)
+    lut = torch.empty(1 << 24, dtype=torch.uint8, device=dev)
+    idx_host = torch.empty(sum(Ks), dtype=torch.int32).pin_memory()
+    idx_dev = torch.empty(sum(Ks), dtype=torch.int32, device=dev)
+
+    def step(record=None):
+        wsm.reduce_colors_into(img, colors, counts, nu, ws)
+        n_unique = int(nu.item())  # the caller needs N' to draw the initial subset
+        col, cnt = colors[:n_unique], counts[:n_unique]
+        off = 0
+        for K in Ks:
+            idx_host[off:off + K] = torch.from_numpy(
+                synth.init_indices(args.seed, n_unique, K).astype(np.int32))
+            off += K
+        idx_dev.copy_(idx_host, non_blocking=True)
+        off = 0
+        out = {}
+        for K in Ks:
+            pal = wsm.palette_from_indices(col, idx_dev[off:off + K])
+            off += K
+            st = wsm.init(col, cnt, N, pal)
+            st.iterate(MAX_ITERS, EPS)
+            index, _, mse = wsm.map_pixels(st, img, lut=lut)
+            out[K] = (st, mse, pal)
+        return n_unique, out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        n_unique, out = step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    ms_step_wall = wall * 1000.0 / args.steps
+
+    per_k = {}
+    color_iters = 0
+    for K in Ks:
+        st, mse, pal = out[K]
+        info = st.info()
+        sse, ev = st.history()
+        color_iters += n_unique * info["iters"]
+        per_k[str(K)] = dict(iters=info["iters"], converged=info["converged"],
+                             mse=float(mse.item()),
+                             evals_per_color_first=float(ev[0] / n_unique),
+                             evals_per_color_last=float(ev[-1] / n_unique))
+    value = color_iters / (ms_step * 1e-3)
+
+    # ---- per-phase times and the full-search comparators (separate passes)
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    col, cnt = colors[:n_unique], counts[:n_unique]
+    phases = {"reduce_ms": timed(lambda: wsm.reduce_colors_into(img, colors, counts, nu, ws))}
+    comparators = {}
+    for K in Ks:
+        st, mse, pal = out[K]
+        iters = st.info()["iters"]
+
+        def run_sm(pal=pal):
+            s = wsm.init(col, cnt, N, pal)
+            s.iterate(MAX_ITERS, EPS)
+            return s
+
+        t_sm = timed(run_sm)
+        phases[f"iterate_ms_k{K}"] = t_sm
+        phases[f"map_ms_k{K}"] = timed(lambda st=st: wsm.map_pixels(st, img, lut=lut))
+        if args.no_comparators:
+            continue
+        holder = {}
+
+        def run_full(pal=pal):
+            s = wsm.init(col, cnt, N, pal)
+            s.iterate_full(MAX_ITERS, EPS)
+            holder["full"] = s
+
+        def run_pix(pal=pal):
+            s = wsm.init_pixels(img, pal)
+            s.iterate_full(MAX_ITERS, EPS)
+            holder["pix"] = s
+
+        t_full = timed(run_full)
+        t_pix = timed(run_pix, reps=2)
+        p_sm = st.palette().cpu().numpy()
+        same_full = bool(np.array_equal(p_sm, holder["full"].palette().cpu().numpy()))
+        same_pix = bool(np.array_equal(p_sm, holder["pix"].palette().cpu().numpy()))
+        _, _, mse_full = wsm.map_pixels(holder["full"], img, lut=lut)
+        comparators[str(K)] = dict(
+            wsm_iterate_ms=t_sm, full_weighted_ms=t_full, full_pixels_ms=t_pix,
+            iters_full=holder["full"].info()["iters"], iters_pixels=holder["pix"].info()["iters"],
+            speedup_vs_full_weighted=t_full / t_sm, speedup_vs_full_pixels=t_pix / t_sm,
+            full_weighted_color_iters_per_s=n_unique * holder["full"].info()["iters"] / (t_full * 1e-3),
+            full_pixels_pixel_iters_per_s=N * holder["pix"].info()["iters"] / (t_pix * 1e-3),
+            equal_palette_full=same_full, equal_palette_pixels=same_pix,
+            mse_wsm=float(out[K][1].item()), mse_full=float(mse_full.item()))
+
+    # ---- roofline of the dominant kernel: the sort-means search, timed per
+    # launch with events on its stream; algorithmic bytes per color per
+    # iteration = 4 (key) + 4 (count) + 1 (membership read) + 1 (write).
+    launches = []
+    for K in Ks:
+        st, mse, pal = out[K]
+        with wsm.kernel_timer("search", capacity=MAX_ITERS) as kt:
+            s = wsm.init(col, cnt, N, pal)
+            s.iterate(MAX_ITERS, EPS)
+        it = s.info()["iters"]
+        launches += kt.ms[:it]
+    dur_ms = float(np.mean(launches))
+    bytes_per_launch = 10.0 * n_unique
+    achieved = bytes_per_launch / (dur_ms * 1e-3) / 1e9
+    roofline = dict(kernel="search_kernel", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
+                    avg_launch_us=dur_ms * 1e3, launches=len(launches),
+                    bytes_per_launch=bytes_per_launch)
+
+    large = None
+    if not args.no_large:
+        large = bench_large(args, torch, wsm, synth)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args, img_np, Ks, n_unique)
+
+    line = {
+        "metric": "WSM color-iterations/s and images/s vs full-search GPU k-means at equal MSE",
+        "value": value,
+        "unit": "color-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "ms_per_step_wall": ms_step_wall,
+        "images_per_s": len(Ks) / (ms_step * 1e-3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512x512 sinusoid-field image (seed %d), K in %s, WSM-C eps=1e-4, "
+                               "max 50 iterations; reduce + init + iterate + map per step"
+                               % (args.seed, Ks),
+                   "n_pixels": N, "n_unique": n_unique, "ks": Ks},
+        "per_k": per_k,
+        "phases_ms": phases,
+        "comparators": comparators,
+        "roofline": roofline,
+        "roofline_large": large,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_large(args, torch, wsm, synth):
+    """Reduction and pixel map on the 4096x4096 workload (~2M unique colors,
+    K = 256), each kernel timed per launch with events on its stream."""
+    dev = torch.device("cuda:0")
+    img_np = synth.workload_image("large", 0)
+    N = img_np.shape[0] * img_np.shape[1]
+    img = torch.from_numpy(img_np).to(dev)
+    colors = torch.empty(min(N, 1 << 24), dtype=torch.int32, device=dev)
+    counts = torch.empty_like(colors)
+    nu = torch.empty(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(wsm.reduce_workspace_bytes(N), dtype=torch.uint8, device=dev)
+    lut = torch.empty(1 << 24, dtype=torch.uint8, device=dev)
+    reps = 10
+    for _ in range(2):
+        wsm.reduce_colors_into(img, colors, counts, nu, ws)
+    torch.cuda.synchronize()
+    timers = {}
+    with wsm.kernel_timer("reduce_partition", reps) as kp:
+        for _ in range(reps):
+            wsm.reduce_colors_into(img, colors, counts, nu, ws)
+    with wsm.kernel_timer("reduce_compact", reps) as kc:
+        for _ in range(reps):
+            wsm.reduce_colors_into(img, colors, counts, nu, ws)
+    n_unique = int(nu.item())
+    col, cnt = colors[:n_unique], counts[:n_unique]
+    pal = wsm.palette_from_indices(col, synth.init_indices(0, n_unique, 256))
+    st = wsm.init(col, cnt, N, pal)
+    t_iter = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_iter[0].record()
+    st.iterate(10, 0.0)
+    t_iter[1].record()
+    with wsm.kernel_timer("map_gather", reps) as kg:
+        for _ in range(reps):
+            wsm.map_pixels(st, img, lut=lut, want_mse=False)
+    with wsm.kernel_timer("map_assign", reps) as ka:
+        for _ in range(reps):
+            wsm.map_pixels(st, img, lut=lut, want_mse=False)
+    torch.cuda.synchronize()
+    t_part = float(np.mean(kp.ms))
+    t_comp = float(np.mean(kc.ms))
+    t_gather = float(np.mean(kg.ms))
+    t_assign = float(np.mean(ka.ms))
+    red_bytes = 3.0 * N + 8.0 * n_unique
+    map_bytes = 4.0 * N
+    red_t = t_part + t_comp
+    out = dict(
+        workload="4096x4096 sinusoid-field image (seed 0, noise sigma 12), K=256",
+        n_pixels=N, n_unique=n_unique,
+        reduce=dict(bound="hbm", achieved=red_bytes / (red_t * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=red_bytes / (red_t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    partition_us=t_part * 1e3, compact_us=t_comp * 1e3, bytes=red_bytes),
+        map_gather=dict(bound="hbm", achieved=map_bytes / (t_gather * 1e-3) / 1e9,
+                        peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=map_bytes / (t_gather * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        avg_launch_us=t_gather * 1e3, bytes=map_bytes),
+        map_assign_us=t_assign * 1e3,
+        iterate_10_ms=t_iter[0].elapsed_time(t_iter[1]),
+    )
+    sse, ev = st.history()
+    out["evals_per_color_per_iter"] = [float(e / n_unique) for e in ev]
+    return out
+
+
+def cpu_baseline(args, img_np, Ks, n_unique_gpu):
+    """The FP64 oracle (plain C, one thread) on whole steps of the same
+    workload, repeated until about `cpu_seconds` of CPU time."""
+    import oracle
+    import synth
+
+    N = img_np.shape[0] * img_np.shape[1]
+    t0 = time.perf_counter()
+    steps = 0
+    color_iters = 0
+    while True:
+        col, cnt = oracle.reduce_colors(img_np)
+        for K in Ks:
+            pal = synth.unpack_keys_to_palette(col[synth.init_indices(args.seed, len(col), K)])
+            r = oracle.wsm(col, cnt, N, pal, MAX_ITERS, EPS)
+            oracle.map_pixels(img_np, col, r["m"], r["centers"])
+            color_iters += len(col) * r["iters"]
+        steps += 1
+        if time.perf_counter() - t0 >= args.cpu_seconds:
+            break
+    dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(value=color_iters / dt, unit="color-iterations/s", cores=1, kind="oracle",
+                sample=f"{steps} whole steps (reduce + K in {Ks} x (WSM-C + map)) of the same "
+                       f"512x512 image, {dt:.1f} s, single-threaded C, {model}, "
+                       f"host has {os.cpu_count()} logical CPUs",
+                images_per_s=steps * len(Ks) / dt)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+// Pixel mapping (Sec. 1: the second phase of color quantization) and the MSE
+// of Sec. 3.1, on gfx950.
+//
+//   rows    M for the final palette (the rows kernel of the iteration, in
+//           map mode).
+//   assign  one lane per unique color: a sort-means scan against the final
+//           palette from the color's last membership gives its palette
+//           index, scattered into a 2^24-entry byte table at the color's key;
+//           count * distance is summed per block for the MSE.
+//   gather  16 pixels per lane: three 16-byte loads, 16 table lookups, one
+//           16-byte store of indices (and 48 bytes of rounded palette colors
+//           when asked for).  Block 0 also sums the MSE partials.
+#include "wsm_internal.h"
+
+int wsm_internal_rows_for_map(const wsm_problem *prob, hipStream_t stream);
+
+namespace wsm {
+
+constexpr int kMapThreads = 256;
+constexpr int kGatherPpt = 16;
+
+__global__ __launch_bounds__(kMapThreads) void map_assign_kernel(
+    StateView sv, const uint32_t *__restrict__ colors, const uint32_t *__restrict__ counts,
+    int64_t n, int K, uint8_t *__restrict__ lut) {
+    __shared__ float4 cen[kMaxK];
+    __shared__ double dscr[kMapThreads / 64];
+    const int tid = threadIdx.x;
+    for (int c = tid; c < K; c += kMapThreads) cen[c] = sv.pal[c];
+    __syncthreads();
+    double acc = 0.0;
+    uint32_t ev = 0;
+    const int64_t stride = (int64_t)gridDim.x * kMapThreads;
+    for (int64_t idx = (int64_t)blockIdx.x * kMapThreads + tid; idx < n; idx += stride) {
+        const uint32_t key = colors[idx];
+        float x, y, z;
+        unpack_key(key, x, y, z);
+        const int p = sv.m[idx];
+        float bd;
+        const int best = sm_scan(x, y, z, p, K, cen, sv.rows, bd, ev);
+        lut[key] = (uint8_t)best;
+        acc += (double)counts[idx] * (double)bd;
+    }
+    const double s = block_sum_double<kMapThreads>(acc, dscr);
+    if (tid == 0) sv.map_part[blockIdx.x] = s;
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(kMapThreads) void map_gather_kernel(
+    const uint8_t *__restrict__ rgb, int64_t n, const uint8_t *__restrict__ lut,
+    uint8_t *__restrict__ index_out, uint8_t *__restrict__ rgb_out, double *__restrict__ mse_out,
+    const double *__restrict__ map_part, int nparts, const float4 *__restrict__ pal, int K) {
+    __shared__ uint32_t rpal[kMaxK];  // rounded palette colors, packed 0x00RRGGBB
+    const int tid = threadIdx.x;
+    if (rgb_out) {
+        for (int c = tid; c < kMaxK; c += kMapThreads) {
+            uint32_t v = 0u;
+            if (c < K) {
+                const float4 q = pal[c];
+                const float r = fminf(fmaxf(rintf(q.x), 0.f), 255.f);
+                const float g = fminf(fmaxf(rintf(q.y), 0.f), 255.f);
+                const float b = fminf(fmaxf(rintf(q.z), 0.f), 255.f);
+                v = ((uint32_t)r << 16) | ((uint32_t)g << 8) | (uint32_t)b;
+            }
+            rpal[c] = v;
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && mse_out && tid < 64) {
+        double s = 0.0;
+        for (int g = tid; g < nparts; g += 64) s += map_part[g];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (tid == 0) *mse_out = s / (double)n;
+    }
+    const int64_t first = ((int64_t)blockIdx.x * kMapThreads + tid) * kGatherPpt;
+    if (first >= n) return;
+    if (VEC && first + kGatherPpt <= n) {
+        const uint4 *src = (const uint4 *)(rgb + first * 3);
+        const uint4 q0 = src[0], q1 = src[1], q2 = src[2];
+        const uint32_t w[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y,
+                                q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+        uint32_t idx4[4] = {0u, 0u, 0u, 0u};
+        uint32_t out[12] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int j = 0; j < kGatherPpt; ++j) {
+            const int byte = 3 * j;
+            const uint32_t r = (w[byte >> 2] >> (8 * (byte & 3))) & 0xFFu;
+            const uint32_t g = (w[(byte + 1) >> 2] >> (8 * ((byte + 1) & 3))) & 0xFFu;
+            const uint32_t b = (w[(byte + 2) >> 2] >> (8 * ((byte + 2) & 3))) & 0xFFu;
+            const uint32_t id = lut[(r << 16) | (g << 8) | b];
+            idx4[j >> 2] |= id << (8 * (j & 3));
+            if (rgb_out) {
+                const uint32_t c = rpal[id];
+                const uint32_t ch[3] = {(c >> 16) & 0xFFu, (c >> 8) & 0xFFu, c & 0xFFu};
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const int ob = byte + e;
+                    out[ob >> 2] |= ch[e] << (8 * (ob & 3));
+                }
+            }
+        }
+        *(uint4 *)(index_out + first) = make_uint4(idx4[0], idx4[1], idx4[2], idx4[3]);
+        if (rgb_out) {
+            uint4 *dst = (uint4 *)(rgb_out + first * 3);
+            dst[0] = make_uint4(out[0], out[1], out[2], out[3]);
+            dst[1] = make_uint4(out[4], out[5], out[6], out[7]);
+            dst[2] = make_uint4(out[8], out[9], out[10], out[11]);
+        }
+    } else {
+        for (int j = 0; j < kGatherPpt; ++j) {
+            const int64_t q = first + j;
+            if (q >= n) break;
+            const uint8_t *px = rgb + q * 3;
+            const uint32_t id = lut[((uint32_t)px[0] << 16) | ((uint32_t)px[1] << 8) | (uint32_t)px[2]];
+            index_out[q] = (uint8_t)id;
+            if (rgb_out) {
+                const uint32_t c = rpal[id];
+                rgb_out[q * 3 + 0] = (uint8_t)((c >> 16) & 0xFFu);
+                rgb_out[q * 3 + 1] = (uint8_t)((c >> 8) & 0xFFu);
+                rgb_out[q * 3 + 2] = (uint8_t)(c & 0xFFu);
+            }
+        }
+    }
+}
+
+}  // namespace wsm
+
+using namespace wsm;
+
+extern "C" int wsm_map_pixels(const wsm_problem *prob, const uint8_t *rgb, int64_t n_pixels,
+                              uint8_t *lut, uint8_t *index_out, uint8_t *rgb_out,
+                              double *mse_out, hipStream_t stream) {
+    if (!prob || prob->magic != kMagic || !prob->state) return WSM_EINVAL;
+    if (prob->points != WSM_POINTS_COLORS || !prob->colors || !prob->counts) return WSM_EINVAL;
+    if (prob->k < 1 || prob->k > kMaxK || prob->n_points < 1) return WSM_EINVAL;
+    if (prob->state_bytes < state_bytes_for(prob->n_points)) return WSM_ENOSPC;
+    if (!rgb || !lut || !index_out) return WSM_EINVAL;
+    if (n_pixels < 1 || n_pixels != prob->n_pixels) return WSM_EINVAL;
+    StateView sv = make_view(prob->state);
+    (void)hipGetLastError();
+    int rc = wsm_internal_rows_for_map(prob, stream);
+    if (rc != WSM_OK) return rc;
+    int64_t nb = (prob->n_points + kMapThreads - 1) / kMapThreads;
+    if (nb > kMaxGrid) nb = kMaxGrid;
+    timing_before(WSM_KERNEL_MAP_ASSIGN, stream);
+    map_assign_kernel<<<dim3((unsigned)nb), dim3(kMapThreads), 0, stream>>>(
+        sv, prob->colors, prob->counts, prob->n_points, prob->k, lut);
+    timing_after(WSM_KERNEL_MAP_ASSIGN, stream);
+    if (hipGetLastError() != hipSuccess) return WSM_EHIP;
+    const int64_t per_block = (int64_t)kMapThreads * kGatherPpt;
+    const int64_t gb = (n_pixels + per_block - 1) / per_block;
+    const bool vec = (((uintptr_t)rgb & 15u) == 0u) && (((uintptr_t)index_out & 15u) == 0u) &&
+                     (!rgb_out || (((uintptr_t)rgb_out & 15u) == 0u));
+    timing_before(WSM_KERNEL_MAP_GATHER, stream);
+    if (vec)
+        map_gather_kernel<true><<<dim3((unsigned)gb), dim3(kMapThreads), 0, stream>>>(
+            rgb, n_pixels, lut, index_out, rgb_out, mse_out, sv.map_part, (int)nb, sv.pal, prob->k);
+    else
+        map_gather_kernel<false><<<dim3((unsigned)gb), dim3(kMapThreads), 0, stream>>>(
+            rgb, n_pixels, lut, index_out, rgb_out, mse_out, sv.map_part, (int)nb, sv.pal, prob->k);
+    timing_after(WSM_KERNEL_MAP_GATHER, stream);
+    if (hipGetLastError() != hipSuccess) return WSM_EHIP;
+    return WSM_OK;
+}

@@ -1,0 +1,225 @@
+// Internal definitions shared by the gfx950 kernels of the WSM library:
+// state layout, launch constants and the small device helpers every step
+// uses.  Nothing here is part of the C ABI (see include/wsm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/wsm.h"
+
+namespace wsm {
+
+constexpr int kMaxK = WSM_MAX_K;
+constexpr int kHistory = WSM_HISTORY;
+constexpr int kMaxGrid = 2048;          // upper bound on search-kernel blocks
+constexpr int kSearchThreads = 1024;    // threads per search block (16 waves)
+constexpr int kRowThreads = 256;        // threads per rows block (one per center)
+constexpr uint32_t kMagic = 0x574D5331u;
+
+constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Measurement hook (timing.hip): no-ops unless a caller attached events to
+// this kernel kind.
+void timing_before(int kind, hipStream_t stream);
+void timing_after(int kind, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Per-iteration record.  Two copies live in the state header: the kernels of
+// call-relative step i read copy (i & 1) and write copy ((i + 1) & 1), so no
+// block ever reads a record another block of the same launch is writing.
+struct Record {
+    int32_t iters;      // iterations completed (t of the last update)
+    int32_t converged;  // the Sec. 3.2 criterion (or SSE == 0) has fired
+    int32_t err;        // device-side error bits
+    int32_t pad;
+    double sse_last;    // SSE_t of the last completed iteration
+    double pad2;
+};
+static_assert(sizeof(Record) == 32, "record layout");
+
+struct Header {
+    uint32_t magic;
+    int32_t k;
+    int32_t points;
+    int32_t grid;
+    int64_t n_points;
+    int64_t n_pixels;
+    uint64_t reserved[4];
+    Record rec[2];      // bytes 64..127
+    int32_t info[4];    // bytes 128..143: public copy {iters, converged, err, 0}
+};
+static_assert(offsetof(Header, rec) == 64, "header layout");
+static_assert(offsetof(Header, info) == 128, "header layout");
+
+// State layout (byte offsets).  Sizes do not depend on k; only the
+// membership array at the end depends on the number of points.
+constexpr size_t kOffHeader = 0;
+constexpr size_t kOffPalette = 256;                                   // float4[2][256]
+constexpr size_t kOffTotals = kOffPalette + 2 * kMaxK * 16;           // u64[3][256][4]
+constexpr size_t kOffSsePart = kOffTotals + 3 * kMaxK * 4 * 8;        // double[2][kMaxGrid]
+constexpr size_t kOffEvalPart = kOffSsePart + 2 * kMaxGrid * 8;       // u64[2][kMaxGrid]
+constexpr size_t kOffSseHist = kOffEvalPart + 2 * kMaxGrid * 8;       // double[kHistory]
+constexpr size_t kOffEvalHist = kOffSseHist + kHistory * 8;           // int64[kHistory]
+constexpr size_t kOffRows = kOffEvalHist + kHistory * 8;              // u8[256][256]
+constexpr size_t kOffMapPart = kOffRows + kMaxK * kMaxK;              // double[kMaxGrid]
+constexpr size_t kOffMembership = align_up(kOffMapPart + kMaxGrid * 8, 256);
+
+inline size_t state_bytes_for(int64_t n_points) {
+    return kOffMembership + align_up((size_t)n_points, 256);
+}
+
+// Typed device view of a state block.
+struct StateView {
+    Header *hdr;
+    float4 *pal;          // [2][256]
+    unsigned long long *totals;  // [3][256][4]
+    double *sse_part;     // [2][kMaxGrid]
+    unsigned long long *eval_part;  // [2][kMaxGrid]
+    double *sse_hist;
+    long long *eval_hist;
+    uint8_t *rows;        // [256][256]
+    double *map_part;     // [kMaxGrid]
+    uint8_t *m;           // [n_points]
+};
+
+inline StateView make_view(void *state) {
+    char *b = (char *)state;
+    StateView v;
+    v.hdr = (Header *)(b + kOffHeader);
+    v.pal = (float4 *)(b + kOffPalette);
+    v.totals = (unsigned long long *)(b + kOffTotals);
+    v.sse_part = (double *)(b + kOffSsePart);
+    v.eval_part = (unsigned long long *)(b + kOffEvalPart);
+    v.sse_hist = (double *)(b + kOffSseHist);
+    v.eval_hist = (long long *)(b + kOffEvalHist);
+    v.rows = (uint8_t *)(b + kOffRows);
+    v.map_part = (double *)(b + kOffMapPart);
+    v.m = (uint8_t *)(b + kOffMembership);
+    return v;
+}
+
+// Points a state is bound to: unique colors + counts, or raw pixels.
+struct Points {
+    const uint32_t *colors;
+    const uint32_t *counts;
+    const uint8_t *rgb;
+    int64_t n;
+    int32_t is_pixels;
+};
+
+// ---------------------------------------------------------------------------
+// Squared RGB distance (Eq. 1 uses ||x - c||^2).  One fixed expression is
+// used everywhere -- for the center table, its row sort, the break test and
+// the point distances -- so a distance recomputed in the scan is bit-equal
+// to the one the row was sorted by.  The library is built with
+// -ffp-contract=off; the two fused multiply-adds are explicit.
+__device__ __forceinline__ float sq_dist(float ax, float ay, float az,
+                                         float bx, float by, float bz) {
+    float dx = ax - bx;
+    float dy = ay - by;
+    float dz = az - bz;
+    return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}
+
+// Break test of the sort-means scan: stop at center t once
+// d(c_p, c_t)^2 >= 4 d(x, c_p)^2 (triangle inequality, Sec. 2).  The float32
+// test is made conservative by a factor 1 + 2^-16 so that rounding in the
+// three squared distances can never skip a center that the float32 full
+// search would choose (the rounding error of each is below 2^-21 relative).
+constexpr float kBreakScale = 4.0f * (1.0f + 1.0f / 65536.0f);
+
+// Tie key (dist, k != p, k): on equal distance keep the previous center p,
+// otherwise prefer the lower index.  t is never p.
+__device__ __forceinline__ bool better_center(float d, float best_d, int t,
+                                              int best, int p) {
+    return d < best_d || (d == best_d && best != p && t < best);
+}
+
+__device__ __forceinline__ void unpack_key(uint32_t key, float &r, float &g,
+                                           float &b) {
+    r = (float)((key >> 16) & 0xFFu);
+    g = (float)((key >> 8) & 0xFFu);
+    b = (float)(key & 0xFFu);
+}
+
+// Sort-means scan of row p of M (Alg. 2 inner loop).  Returns the best
+// center and its distance; `ev` counts point-center distances evaluated.
+__device__ __forceinline__ int sm_scan(float x, float y, float z, int p, int K,
+                                       const float4 *cen, const uint8_t *rows,
+                                       float &best_d, uint32_t &ev) {
+    const float4 cp = cen[p];
+    const float prev = sq_dist(x, y, z, cp.x, cp.y, cp.z);
+    const float thr = prev * kBreakScale;
+    float bd = prev;
+    int best = p;
+    ev += 1;
+    const uint32_t *row = (const uint32_t *)(rows + (size_t)p * kMaxK);
+    bool active = K > 1;
+    for (int q = 0; active && 4 * q < K; ++q) {
+        const uint32_t w = row[q];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = 4 * q + u;
+            if (active && j >= 1) {
+                if (j >= K) {
+                    active = false;
+                } else {
+                    const int t = (int)((w >> (8 * u)) & 0xFFu);
+                    const float4 ct = cen[t];
+                    const float dpt = sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z);
+                    if (dpt >= thr) {
+                        active = false;
+                    } else {
+                        const float d = sq_dist(x, y, z, ct.x, ct.y, ct.z);
+                        ev += 1;
+                        if (better_center(d, bd, t, best, p)) {
+                            bd = d;
+                            best = t;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    best_d = bd;
+    return best;
+}
+
+// Sum of a double over a block in a fixed order (deterministic): each wave
+// reduces by a fixed butterfly, then wave sums are added in wave order.
+template <int NT>
+__device__ __forceinline__ double block_sum_double(double v, double *scratch) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) scratch[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < NT / 64; ++w) s += scratch[w];
+    }
+    __syncthreads();
+    return s;  // valid in thread 0 only
+}
+
+template <int NT>
+__device__ __forceinline__ unsigned long long block_sum_u64(
+    unsigned long long v, unsigned long long *scratch) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) scratch[wave] = v;
+    __syncthreads();
+    unsigned long long s = 0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < NT / 64; ++w) s += scratch[w];
+    }
+    __syncthreads();
+    return s;
+}
+
+}  // namespace wsm

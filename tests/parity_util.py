@@ -1,0 +1,61 @@
+"""Comparison helpers for GPU-vs-oracle parity (the tolerances of the tests).
+
+* Unique-color tables: bit-exact.
+* Assignments, given identical centers: the GPU's choice k_g must satisfy
+  d64(x, c_kg) <= (1 + 1e-6) min_k d64(x, c_k); and k_g must equal the
+  oracle's choice wherever the best and second-best float64 distances differ
+  by more than 1e-6 relative ("near-ties" are the rest).
+* Centers, given identical assignments: within 1e-4 per channel (8-bit units).
+* Final MSE: within 1e-5 relative.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+NEAR_TIE = 1e-6
+CENTER_TOL = 1e-4
+MSE_RTOL = 1e-5
+
+
+def unpack(keys) -> np.ndarray:
+    k = np.asarray(keys).astype(np.int64) & 0xFFFFFF
+    return np.stack([(k >> 16) & 255, (k >> 8) & 255, k & 255], 1).astype(np.float64)
+
+
+def all_dists(x: np.ndarray, c: np.ndarray) -> np.ndarray:
+    """float64 squared distances [n, K]."""
+    d = np.zeros((x.shape[0], c.shape[0]), dtype=np.float64)
+    for ch in range(3):
+        d += (x[:, ch:ch + 1] - c[None, :, ch]) ** 2
+    return d
+
+
+def check_assignment(x: np.ndarray, centers: np.ndarray, m_gpu: np.ndarray,
+                     m_ref: np.ndarray, chunk: int = 65536) -> dict:
+    """Checks the GPU assignment against the reference under the near-tie
+    rule; returns counts for reporting.  Raises AssertionError on failure."""
+    n = x.shape[0]
+    K = centers.shape[0]
+    mism = 0
+    ties = 0
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        d = all_dists(x[s:e], centers)
+        dmin = d.min(1)
+        g = m_gpu[s:e].astype(np.int64)
+        r = m_ref[s:e].astype(np.int64)
+        dg = d[np.arange(e - s), g]
+        ok_val = dg <= dmin * (1 + NEAR_TIE) + 0.0
+        assert ok_val.all(), f"GPU choice not within near-tie of the minimum at {s + np.flatnonzero(~ok_val)[:5]}"
+        if K > 1:
+            part = np.partition(d, 1, axis=1)
+            second = part[:, 1]
+            clear = second > dmin * (1 + NEAR_TIE)
+        else:
+            clear = np.ones(e - s, dtype=bool)
+        bad = clear & (g != r)
+        assert not bad.any(), f"assignment differs away from ties at {s + np.flatnonzero(bad)[:5]}"
+        mism += int((g != r).sum())
+        ties += int((~clear).sum())
+    return dict(mismatches_at_ties=mism, near_ties=ties)

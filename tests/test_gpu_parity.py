@@ -1,0 +1,415 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Every test prints the case it runs (workload, seed, shape, entry point)
+before touching the GPU.  Inputs are the seeded synthetic images of synth/.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity_util import CENTER_TOL, MSE_RTOL, check_assignment, unpack
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _wsm():
+    import paper_1011_0093_amd as wsm
+    return wsm
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _gpu_img(img):
+    return torch.from_numpy(np.ascontiguousarray(img)).cuda()
+
+
+def _u32(t):
+    return t.cpu().numpy().astype(np.int64).astype(np.uint32)
+
+
+# ---------------------------------------------------------------------------
+# Data reduction: bit-exact.
+
+REDUCE_CASES = [
+    ("small", 0), ("small", 3), ("medium", 0), ("medium", 2),
+]
+
+
+@pytest.mark.parametrize("name,seed", REDUCE_CASES)
+def test_reduce_bit_exact_workloads(name, seed):
+    wsm = _wsm()
+    img = synth.workload_image(name, seed)
+    _say("reduce", name, seed, img.shape)
+    col, cnt = wsm.reduce_colors(_gpu_img(img))
+    rc, rn = oracle.reduce_colors(img)
+    assert np.array_equal(_u32(col), rc)
+    assert np.array_equal(_u32(cnt), rn)
+
+
+@pytest.mark.parametrize("shape,kind", [
+    ((1, 1, 3), "one"), ((7, 5, 3), "const"), ((1000, 7, 3), "noise"),
+    ((333, 77, 3), "noise"), ((64, 64, 3), "two"), ((1024, 1024, 3), "noise"),
+    ((700, 701, 3), "coarse"),
+])
+def test_reduce_edge_cases(shape, kind):
+    wsm = _wsm()
+    rng = np.random.default_rng(hash((shape, kind)) & 0xFFFF)
+    if kind == "one":
+        img = np.array([[[1, 2, 3]]], dtype=np.uint8)
+    elif kind == "const":
+        img = np.full(shape, 200, dtype=np.uint8)
+    elif kind == "two":
+        img = np.zeros(shape, dtype=np.uint8)
+        img[::2] = (255, 255, 255)
+    elif kind == "coarse":
+        img = (rng.integers(0, 4, size=shape) * 85).astype(np.uint8)
+    else:
+        img = rng.integers(0, 256, size=shape, dtype=np.uint8)
+    _say("reduce edge", shape, kind)
+    col, cnt = wsm.reduce_colors(_gpu_img(img))
+    rc, rn = oracle.reduce_colors(img)
+    assert np.array_equal(_u32(col), rc) and np.array_equal(_u32(cnt), rn)
+
+
+def test_reduce_unaligned_input_and_full_size():
+    wsm = _wsm()
+    img = synth.workload_image("large", 0)
+    _say("reduce large 4096x4096 seed 0 (aligned) and unaligned 1-byte offset")
+    g = _gpu_img(img)
+    col, cnt = wsm.reduce_colors(g)
+    rc, rn = oracle.reduce_colors(img)
+    assert np.array_equal(_u32(col), rc) and np.array_equal(_u32(cnt), rn)
+    # an image that starts one byte into a buffer takes the unaligned path
+    sub = img[:1024, :1000].copy()
+    buf = torch.empty(sub.size + 16, dtype=torch.uint8, device="cuda")
+    view = buf[1:1 + sub.size]
+    view.copy_(torch.from_numpy(sub.reshape(-1)).cuda())
+    col, cnt = wsm.reduce_colors(view)
+    rc, rn = oracle.reduce_colors(sub)
+    assert np.array_equal(_u32(col), rc) and np.array_equal(_u32(cnt), rn)
+
+
+# ---------------------------------------------------------------------------
+# Iterations, lock-step: one GPU iteration at a time, the oracle redoes each
+# step from the GPU's own float32 centers and memberships.
+
+def _lockstep(img, K, seed, iters, full=False, check_evals=True):
+    wsm = _wsm()
+    g = _gpu_img(img)
+    col, cnt = wsm.reduce_colors(g)
+    colors = _u32(col)
+    counts = _u32(cnt)
+    n_pix = img.shape[0] * img.shape[1]
+    idx = synth.init_indices(seed, len(colors), K)
+    pal = wsm.palette_from_indices(col, idx)
+    st = wsm.init(col, cnt, n_pix, pal)
+    x = unpack(colors)
+    m_prev = np.zeros(len(colors), dtype=np.uint8)
+    c_prev = pal.cpu().numpy().astype(np.float64)
+    stats = []
+    for t in range(1, iters + 1):
+        if full:
+            st.iterate_full(1, 0.0)
+        else:
+            st.iterate(1, 0.0)
+        info = st.info()
+        if info["converged"]:
+            break
+        m_gpu = st.membership().cpu().numpy()
+        c_gpu = st.palette().cpu().numpy().astype(np.float64)
+        m_ref, mind, ev_ref = oracle.search_step(colors, c_prev, m_prev)
+        if len(colors) > 300000:
+            sel = np.random.default_rng(t).choice(len(colors), size=200000, replace=False)
+            s = check_assignment(x[sel], c_prev, m_gpu[sel], m_ref[sel])
+        else:
+            s = check_assignment(x, c_prev, m_gpu, m_ref)
+        # update from the GPU's own assignment: exact integer sums vs float64
+        c_ref = oracle.update_step(colors, counts, n_pix, m_gpu, c_prev)
+        err = np.abs(c_gpu - c_ref).max()
+        assert err <= CENTER_TOL, (t, err)
+        sse_gpu, ev_gpu = st.history()
+        sse_ref = oracle.weighted_sse(counts, n_pix, mind)
+        assert sse_gpu[-1] == pytest.approx(sse_ref, rel=1e-6), t
+        if check_evals and not full:
+            # same count except where the float32 break test sits on the edge
+            assert abs(int(ev_gpu[-1]) - ev_ref) <= max(2, 1e-3 * ev_ref), (t, ev_gpu[-1], ev_ref)
+        s.update(t=t, center_err=float(err), evals_gpu=int(ev_gpu[-1]), evals_ref=ev_ref)
+        stats.append(s)
+        m_prev, c_prev = m_gpu, c_gpu
+    return stats
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_lockstep_small_k32(seed):
+    img = synth.workload_image("small", seed)
+    _say("lockstep small", seed, "K=32")
+    stats = _lockstep(img, 32, seed, 12)
+    print(stats[-1])
+
+
+@pytest.mark.parametrize("K", [16, 64, 256])
+def test_lockstep_medium(K):
+    img = synth.workload_image("medium", 0)
+    _say("lockstep medium seed 0 K", K)
+    stats = _lockstep(img, K, 0, 4)
+    print(stats[-1])
+
+
+def test_lockstep_full_search_comparator():
+    img = synth.workload_image("small", 2)
+    _say("lockstep small seed 2 K=32 full search")
+    _lockstep(img, 32, 2, 6, full=True)
+
+
+# ---------------------------------------------------------------------------
+# End-to-end against the oracle, and the three GPU forms against each other.
+
+def _run_gpu(img, K, seed, max_iters=50, eps=1e-4, mode="sm"):
+    wsm = _wsm()
+    g = _gpu_img(img)
+    col, cnt = wsm.reduce_colors(g)
+    n_pix = img.shape[0] * img.shape[1]
+    idx = synth.init_indices(seed, col.numel(), K)
+    pal = wsm.palette_from_indices(col, idx)
+    if mode == "pixels":
+        st = wsm.init_pixels(g, pal)
+        st.iterate_full(max_iters, eps)
+    else:
+        st = wsm.init(col, cnt, n_pix, pal)
+        if mode == "sm":
+            st.iterate(max_iters, eps)
+        else:
+            st.iterate_full(max_iters, eps)
+    return st, col, cnt, pal
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_end_to_end_small_vs_oracle(seed):
+    """WSM-C (eps 1e-4, at most 50 iterations) on the GPU in float32 against a
+    free-running float64 oracle.  Every GPU iteration is also checked in
+    lock-step.  While the two assignment histories are identical the final
+    MSE must agree to 1e-5 relative; if they part, the first differing
+    assignment must be explained by the centers' rounding difference: its
+    float64 distance gap is at most (||x-c_a|| + ||x-c_b||) * ||c_gpu - c_ref||
+    for the two candidate centers (a near-tie of the two runs)."""
+    wsm = _wsm()
+    img = synth.workload_image("small", seed)
+    n_pix = img.shape[0] * img.shape[1]
+    _say("e2e small", seed, "K=32 eps=1e-4 max 50")
+    g = _gpu_img(img)
+    col, cnt = wsm.reduce_colors(g)
+    colors, counts = _u32(col), _u32(cnt)
+    x = unpack(colors)
+    pal = wsm.palette_from_indices(col, synth.init_indices(seed, len(colors), 32))
+    st = wsm.init(col, cnt, n_pix, pal)
+    c_ref = pal.cpu().numpy().astype(np.float64)
+    c_gpu_prev = c_ref.copy()
+    m_ref = np.zeros(len(colors), np.uint8)
+    m_gpu_prev = m_ref.copy()
+    sse_prev = None
+    parted_at = None
+    ref_iters, ref_conv = 50, False
+    for t in range(1, 51):
+        # free-running float64 oracle, one step (Alg. 2 with the Sec. 3.2 stop)
+        m_new, mind, _ = oracle.search_step(colors, c_ref, m_ref)
+        sse = oracle.weighted_sse(counts, n_pix, mind)
+        c_new = oracle.update_step(colors, counts, n_pix, m_new, c_ref)
+        # GPU step
+        st.iterate(1, 1e-4)
+        m_gpu = st.membership().cpu().numpy()
+        c_gpu = st.palette().cpu().numpy().astype(np.float64)
+        if parted_at is None and not np.array_equal(m_gpu, m_new):
+            parted_at = t
+            diff = np.flatnonzero(m_gpu != m_new)
+            dc = np.sqrt(((c_gpu_prev - c_ref) ** 2).sum(1)).max()
+            d = ((x[diff, None, :] - c_ref[None, :, :]) ** 2).sum(2)
+            ka, kb = m_gpu[diff].astype(int), m_new[diff].astype(int)
+            da, db = d[np.arange(len(diff)), ka], d[np.arange(len(diff)), kb]
+            # |d_gpu(k) - d_ref(k)| <= (2 sqrt(d_ref(k)) + dc) dc for each of the
+            # two centers, plus float32 rounding of the GPU's own distances
+            bound = 2 * (np.sqrt(da) + np.sqrt(db)) * dc + 2 * dc * dc + 1e-6 * np.maximum(da, db)
+            print(dict(parted_at=t, n_diff=len(diff), max_gap=float(np.abs(da - db).max()),
+                       center_diff=float(dc)))
+            assert (np.abs(da - db) <= bound).all()
+        m_ref, c_ref = m_new, c_new
+        m_gpu_prev, c_gpu_prev = m_gpu, c_gpu
+        stop = sse == 0.0 or (t >= 2 and (sse_prev - sse) / sse <= 1e-4)
+        sse_prev = sse
+        info = st.info()
+        if parted_at is None:
+            assert bool(info["converged"]) == stop
+        if stop:
+            ref_iters, ref_conv = t, True
+        if stop or info["converged"]:
+            break
+    idx, _, mse = wsm.map_pixels(st, g)
+    _, mse_ref = oracle.map_pixels(img, colors, m_ref, c_ref)
+    print(dict(gpu_iters=info["iters"], ref_iters=ref_iters, parted_at=parted_at,
+               mse=float(mse.item()), mse_ref=mse_ref))
+    if parted_at is None:
+        assert info["iters"] == ref_iters
+        assert float(mse.item()) == pytest.approx(mse_ref, rel=MSE_RTOL)
+        assert np.abs(st.palette().cpu().numpy() - c_ref).max() <= CENTER_TOL
+    # the GPU result is itself checked against the oracle on its own palette
+    c_fin = st.palette().cpu().numpy().astype(np.float64)
+    _, mse_own = oracle.map_pixels(img, colors, st.membership().cpu().numpy(), c_fin)
+    assert float(mse.item()) == pytest.approx(mse_own, rel=MSE_RTOL)
+    sse_h, _ = st.history()
+    assert info["iters"] == len(sse_h)
+
+
+@pytest.mark.parametrize("name,seed,K", [("small", 0, 32), ("medium", 1, 64)])
+def test_pruned_full_and_pixel_kmeans_identical(name, seed, K):
+    img = synth.workload_image(name, seed)
+    _say("three GPU forms", name, seed, K)
+    a, *_ = _run_gpu(img, K, seed, 30, 1e-4, "sm")
+    b, *_ = _run_gpu(img, K, seed, 30, 1e-4, "full")
+    c, *_ = _run_gpu(img, K, seed, 30, 1e-4, "pixels")
+    pa, pb, pc = (s.palette().cpu().numpy() for s in (a, b, c))
+    assert np.array_equal(pa, pb)
+    assert np.array_equal(pa, pc)
+    assert np.array_equal(a.membership().cpu().numpy(), b.membership().cpu().numpy())
+    ia, ib, ic = a.info(), b.info(), c.info()
+    assert ia["iters"] == ib["iters"] == ic["iters"]
+    sa, ea = a.history()
+    sb, eb = b.history()
+    np.testing.assert_array_equal(sa, sb)
+    assert (ea <= eb).all() and ea[-1] < eb[-1]
+
+
+def test_resume_equals_single_call():
+    img = synth.workload_image("small", 1)
+    _say("resume 4+6 vs 10, small seed 1 K=24")
+    a, *_ = _run_gpu(img, 24, 1, 10, 0.0)
+    wsm = _wsm()
+    g = _gpu_img(img)
+    col, cnt = wsm.reduce_colors(g)
+    pal = wsm.palette_from_indices(col, synth.init_indices(1, col.numel(), 24))
+    b = wsm.init(col, cnt, img.shape[0] * img.shape[1], pal)
+    b.iterate(4, 0.0)
+    assert b.info()["iters"] == 4 and not b.info()["converged"]
+    b.iterate(6, 0.0)
+    assert np.array_equal(a.palette().cpu().numpy(), b.palette().cpu().numpy())
+    assert a.info() == b.info()
+    np.testing.assert_array_equal(a.history()[0], b.history()[0])
+
+
+# ---------------------------------------------------------------------------
+# Degenerate cases.
+
+def test_k1_and_exact_palette():
+    wsm = _wsm()
+    img = synth.workload_image("small", 3)
+    _say("K=1 small seed 3")
+    st, col, cnt, pal = _run_gpu(img, 1, 3, 10, 1e-4)
+    px = img.reshape(-1, 3).astype(np.float64)
+    np.testing.assert_allclose(st.palette().cpu().numpy()[0], px.mean(0), atol=CENTER_TOL)
+    assert st.info()["iters"] == 3 and st.info()["converged"]
+    idx, _, mse = wsm.map_pixels(st, _gpu_img(img))
+    assert (idx.cpu().numpy() == 0).all()
+    assert float(mse.item()) == pytest.approx(px.var(0).sum(), rel=MSE_RTOL)
+    # an image of exactly K colors started from those colors: zero error at t=1
+    rng = np.random.default_rng(4)
+    palc = np.unique(rng.integers(0, 256, size=(40, 3)), axis=0).astype(np.uint8)
+    K = palc.shape[0]
+    img2 = palc[rng.integers(0, K, size=(64, 50))]
+    _say("exact palette K", K)
+    st2, col2, cnt2, pal2 = _run_gpu(img2, K, 0, 50, 1e-4)
+    assert st2.info() == dict(iters=1, converged=True, err=0)
+    idx2, rgb2, mse2 = wsm.map_pixels(st2, _gpu_img(img2), want_rgb=True)
+    assert float(mse2.item()) == 0.0
+    assert np.array_equal(rgb2.cpu().numpy(), img2)
+
+
+def test_empty_cluster_keeps_center():
+    wsm = _wsm()
+    img = np.zeros((8, 8, 3), dtype=np.uint8)
+    img[:, 4:6] = (10, 0, 0)
+    img[:, 6:] = (20, 0, 0)
+    _say("empty cluster, 3 colors, 3 centers, one far away")
+    g = _gpu_img(img)
+    col, cnt = wsm.reduce_colors(g)
+    init = np.array([[0, 0, 0], [200, 200, 200], [10, 0, 0]], dtype=np.float32)
+    pal = torch.from_numpy(init).cuda()
+    st = wsm.init(col, cnt, 64, pal)
+    st.iterate(5, 1e-4)
+    p = st.palette().cpu().numpy()
+    np.testing.assert_array_equal(p[1], init[1])
+    ref = oracle.wsm(_u32(col), _u32(cnt), 64, init.astype(np.float64), 5, 1e-4)
+    np.testing.assert_allclose(p, ref["centers"], atol=CENTER_TOL)
+    assert st.info()["iters"] == ref["iters"]
+    np.testing.assert_allclose(st.history()[0], ref["sse"], rtol=1e-6)
+
+
+def test_invalid_arguments_raise():
+    wsm = _wsm()
+    img = synth.workload_image("small", 0)
+    g = _gpu_img(img)
+    col, cnt = wsm.reduce_colors(g)
+    _say("invalid arguments")
+    pal = torch.zeros((257, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(wsm.WsmError):
+        wsm.init(col, cnt, 65536, pal)
+    few = torch.zeros((3, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(wsm.WsmError):
+        wsm.init(col[:2], cnt[:2], 65536, few)
+    st = wsm.init(col, cnt, 65536, wsm.palette_from_indices(col, [0, 1, 2]))
+    with pytest.raises(wsm.WsmError):
+        st.iterate(0, 1e-4)
+    with pytest.raises(wsm.WsmError):
+        st.iterate(5, float("nan"))
+    with pytest.raises(wsm.WsmError):
+        st.iterate(5, -1.0)
+
+
+# ---------------------------------------------------------------------------
+# Pixel mapping.
+
+@pytest.mark.parametrize("name,seed,K", [("small", 0, 32), ("medium", 2, 256)])
+def test_map_against_oracle(name, seed, K):
+    wsm = _wsm()
+    img = synth.workload_image(name, seed)
+    _say("map", name, seed, K)
+    st, col, cnt, pal = _run_gpu(img, K, seed, 8, 1e-4)
+    idx, rgb_out, mse = wsm.map_pixels(st, _gpu_img(img), want_rgb=True)
+    colors = _u32(col)
+    m = st.membership().cpu().numpy()
+    c = st.palette().cpu().numpy().astype(np.float64)
+    ref_idx, ref_mse = oracle.map_pixels(img, colors, m, c)
+    gi = idx.cpu().numpy()
+    check_assignment(img.reshape(-1, 3).astype(np.float64), c, gi, ref_idx)
+    assert float(mse.item()) == pytest.approx(ref_mse, rel=MSE_RTOL)
+    rp = np.clip(np.rint(c), 0, 255).astype(np.uint8)
+    assert np.array_equal(rgb_out.cpu().numpy().reshape(-1, 3), rp[gi])
+
+
+# ---------------------------------------------------------------------------
+# Full-size image (4096x4096, ~2M unique colors, K=256): lock-step for two
+# iterations on every color, and the map on a sample of pixels.
+
+def test_large_lockstep_and_map_sample():
+    wsm = _wsm()
+    img = synth.workload_image("large", 0)
+    _say("large 4096x4096 seed 0 K=256: 2 lock-step iterations + map sample")
+    stats = _lockstep(img, 256, 0, 2)
+    print(stats)
+    st, col, cnt, pal = _run_gpu(img, 256, 0, 3, 1e-4)
+    idx, _, mse = wsm.map_pixels(st, _gpu_img(img))
+    c = st.palette().cpu().numpy().astype(np.float64)
+    colors = _u32(col)
+    m = st.membership().cpu().numpy()
+    rng = np.random.default_rng(0)
+    sel = rng.choice(img.shape[0] * img.shape[1], size=200000, replace=False)
+    sub = img.reshape(-1, 3)[sel]
+    ref_idx, _ = oracle.map_pixels(sub[:, None, :], colors, m, c)
+    check_assignment(sub.astype(np.float64), c, idx.cpu().numpy()[sel], ref_idx)
+    ci, cmse = oracle.assign_colors(colors, _u32(cnt), img.shape[0] * img.shape[1], m, c)
+    assert float(mse.item()) == pytest.approx(cmse, rel=MSE_RTOL)
