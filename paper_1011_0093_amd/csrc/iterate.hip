@@ -1,29 +1,29 @@
-// Iterations of the weighted sort-means loop (Alg. 2) on gfx950.
+// Iterations of the weighted sort-means loop (Alg. 2) on gfx950: one launch
+// per iteration.
 //
-// One iteration t = call-relative step i is two launches:
-//   rows    K blocks.  Every block applies the weighted center update of the
-//           previous step (Alg. 2, last loop: c_k = sum w x / sum w, here
-//           with exact integer sums of count * channel), evaluates the Sec.
-//           3.2 stopping rule, and then builds row a = blockIdx of the
-//           sorted-neighbour matrix M (Alg. 2: pairwise center distances,
-//           each row sorted by distance, own center first, ties by index).
-//           Block 0 publishes the palette and the iteration record.
-//   search  one block per CU.  Each lane takes one point, starts from its
-//           previous center p, walks M[p] and stops at the first center
-//           with d(c_p,c_t)^2 >= 4 d(x,c_p)^2 (sort-means).  The new
-//           membership is written back and count*(R,G,B,1) is added into
-//           per-block LDS accumulators, which are flushed once per block
-//           with 64-bit device atomics (second level of the reduction).
+// Every block of step i
+//   1. applies the center update of step i-1 (Alg. 2, last loop:
+//      c_k = sum w x / sum w, from exact integer sums of count * channel),
+//      reduces the SSE partials of step i-1 in a fixed order and evaluates the
+//      Sec. 3.2 stopping rule -- redundantly, so all blocks agree without a
+//      grid-wide barrier; block 0 publishes the palette and the record;
+//   2. searches its contiguous chunk of points: sort-means over the
+//      truncated sorted rows it builds in LDS (sm_block.h), or full search
+//      for the comparator;
+//   3. sums count * (R, G, B, 1) per center: runs of equal centers within a
+//      wave are pre-summed with a segmented scan, then added into LDS, and
+//      each block flushes its non-zero sums with 64-bit device atomics (the
+//      second level of the reduction); the block's SSE and evaluation count
+//      go to per-block partials.
+// The sums are exact integers, so the result does not depend on the order
+// of the additions and the pruned search, the full search and k-means on the
+// raw pixels produce bit-identical centers.
 //
-// The full-search comparator fuses the update into its search kernel (one
-// launch per iteration): every block recomputes the K centers from the
-// totals itself, which is cheap, and a full search needs no M.
-//
-// State records and palettes are double-buffered by step parity and the
-// totals are triple-buffered, so no launch reads what another block of the
-// same launch writes.  After the last step a single-block kernel applies the
-// final update and copies the result to the public slot 0.
-#include "wsm_internal.h"
+// Records and palettes are double-buffered by step parity and the totals
+// triple-buffered, so no launch reads what another block of the same launch
+// writes.  A single-block kernel applies the final update after the last
+// step and copies the result to the public slot 0.
+#include "sm_block.h"
 
 namespace wsm {
 
@@ -31,61 +31,95 @@ struct IterArgs {
     StateView sv;
     Points pts;
     int k;
-    int grid;          // blocks of the search kernel (partials per step)
+    int grid;          // blocks of the step kernel (partials per step)
     double eps;
+    int64_t n_pixels;  // sum of the weights
 };
 
-// ---------------------------------------------------------------------------
-// Update phase, run by every block of a rows / fused / final launch.
-// Produces the centers entering the search of step i in `cen` (LDS) and the
-// record after the update.  Block `writer` publishes palette, record and the
-// history entry.  Returns the record (same in every thread of every block).
-template <int NT>
+// Center totals: packed as two u64 (sum cR | sum cG << 32, sum cB | sum c << 32)
+// when 255 * n_pixels < 2^32, else four u64.
+template <bool PACKED>
+__device__ __forceinline__ void totals_to_center(const unsigned long long *T, int c,
+                                                 float4 prev, float4 &out) {
+    unsigned long long sr, sg, sb, w;
+    if (PACKED) {
+        const unsigned long long a = T[c * 4 + 0], b = T[c * 4 + 1];
+        sr = a & 0xFFFFFFFFull;
+        sg = a >> 32;
+        sb = b & 0xFFFFFFFFull;
+        w = b >> 32;
+    } else {
+        sr = T[c * 4 + 0];
+        sg = T[c * 4 + 1];
+        sb = T[c * 4 + 2];
+        w = T[c * 4 + 3];
+    }
+    if (w != 0ull) {
+        const double dw = (double)w;
+        out = make_float4((float)((double)sr / dw), (float)((double)sg / dw),
+                          (float)((double)sb / dw), 0.0f);
+    } else {
+        out = prev;  // empty cluster keeps its center
+    }
+}
+
+// Update phase (see the file comment).  Returns the record after the update,
+// identical in every block.
+template <int NT, bool PACKED>
 __device__ Record update_phase(const IterArgs &a, int i, float4 *cen, bool writer,
                                double *dscr, unsigned long long *uscr) {
+    constexpr int kPer = kMaxK / NT > 0 ? kMaxK / NT : 1;
     const int tid = threadIdx.x;
-    const Header *hdr = a.sv.hdr;
-    const Record rin = hdr->rec[i & 1];
+    const Record rin = a.sv.hdr->rec[i & 1];
     const float4 *pal_in = a.sv.pal + (size_t)(i & 1) * kMaxK;
     float4 *pal_out = a.sv.pal + (size_t)((i + 1) & 1) * kMaxK;
-    Record r = rin;
-    if (i == 0 || rin.converged) {
-        for (int c = tid; c < a.k; c += NT) cen[c] = pal_in[c];
-    } else {
-        const unsigned long long *T = a.sv.totals + (size_t)((i - 1) % 3) * kMaxK * 4;
-        for (int c = tid; c < a.k; c += NT) {
-            const unsigned long long w = T[c * 4 + 3];
-            if (w != 0ull) {
-                const double dw = (double)w;
-                cen[c] = make_float4((float)((double)T[c * 4 + 0] / dw),
-                                     (float)((double)T[c * 4 + 1] / dw),
-                                     (float)((double)T[c * 4 + 2] / dw), 0.0f);
-            } else {
-                cen[c] = pal_in[c];  // empty cluster keeps its center
-            }
+    const int prv = (i + 2) % 3;  // totals slot of step i-1
+    const unsigned long long *T = a.sv.totals + (size_t)prv * kMaxK * 4;
+    // Issue every load first; which values are used is decided afterwards.
+    const bool update = (i != 0) && !rin.converged;
+    float4 cv[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int c = tid + r * NT;
+        cv[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (c < a.k) {
+            const float4 old = pal_in[c];
+            float4 upd;
+            totals_to_center<PACKED>(T, c, old, upd);
+            cv[r].x = update ? upd.x : old.x;
+            cv[r].y = update ? upd.y : old.y;
+            cv[r].z = update ? upd.z : old.z;
         }
+    }
+    double s = 0.0;
+    unsigned long long e = 0;
+    if (tid < 64) {
+        const double *sp = a.sv.sse_part + (size_t)((i + 1) & 1) * kMaxGrid;
+        const unsigned long long *ep = a.sv.eval_part + (size_t)((i + 1) & 1) * kMaxGrid;
+        for (int g = tid; g < a.grid; g += 64) {
+            s += sp[g];
+            e += ep[g];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int c = tid + r * NT;
+        if (c < a.k) cen[c] = cv[r];
+    }
+    Record r = rin;
+    if (update) {
         // Weighted SSE of step i-1 from the per-block partials, reduced by
         // the first wave in a fixed order (identical in every block).
-        const double *sp = a.sv.sse_part + (size_t)((i - 1) & 1) * kMaxGrid;
-        const unsigned long long *ep = a.sv.eval_part + (size_t)((i - 1) & 1) * kMaxGrid;
         if (tid < 64) {
-            double s = 0.0;
-            unsigned long long e = 0;
-            for (int g = tid; g < a.grid; g += 64) {
-                s += sp[g];
-                e += ep[g];
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                s += __shfl_xor(s, off, 64);
-                e += __shfl_xor(e, off, 64);
-            }
-            if (tid == 0) {
+            s = wave_sum_f64(s);
+            e = wave_sum_u64(e);
+            if (tid == 63) {
                 dscr[0] = s;
                 uscr[0] = e;
             }
         }
         __syncthreads();
-        const double sse = dscr[0] / (double)a.sv.hdr->n_pixels;
+        const double sse = dscr[0] / (double)a.n_pixels;
         const long long ev = (long long)uscr[0];
         const int t = rin.iters + 1;
         const bool stop = (sse == 0.0) || (t >= 2 && (rin.sse_last - sse) / sse <= a.eps);
@@ -105,171 +139,169 @@ __device__ Record update_phase(const IterArgs &a, int i, float4 *cen, bool write
     return r;
 }
 
-// ---------------------------------------------------------------------------
-// Rows kernel: update + one row of M per block.  In map mode (map != 0) the
-// centers are taken from the public palette and nothing but M is written.
-__global__ __launch_bounds__(kRowThreads) void rows_kernel(IterArgs a, int i, int map) {
-    __shared__ float4 cen[kMaxK];
-    __shared__ unsigned long long key[kMaxK];
-    __shared__ double dscr[4];
-    __shared__ unsigned long long uscr[4];
-    const int tid = threadIdx.x;
-    const int row = blockIdx.x;
-    if (map) {
-        for (int c = tid; c < a.k; c += kRowThreads) cen[c] = a.sv.pal[c];
-        __syncthreads();
-    } else {
-        const Record r = update_phase<kRowThreads>(a, i, cen, row == 0, dscr, uscr);
-        if (r.converged) return;
-        if (row == 0) {
-            unsigned long long *T = a.sv.totals + (size_t)(i % 3) * kMaxK * 4;
-            for (int c = tid; c < kMaxK * 4; c += kRowThreads) T[c] = 0ull;
-        }
-    }
-    // Row `row` of M: centers ordered by (d(row, b), b != row, b).  The
-    // float bits of a non-negative distance order like the value.
-    const float4 ca = cen[row];
-    for (int b = tid; b < a.k; b += kRowThreads) {
-        const float4 cb = cen[b];
-        const float d = sq_dist(ca.x, ca.y, ca.z, cb.x, cb.y, cb.z);
-        key[b] = ((unsigned long long)__float_as_uint(d) << 32) |
-                 ((unsigned long long)(b != row) << 8) | (unsigned long long)b;
-    }
-    __syncthreads();
-    uint8_t *out = a.sv.rows + (size_t)row * kMaxK;
-    for (int b = tid; b < a.k; b += kRowThreads) {
-        const unsigned long long kb = key[b];
-        int rank = 0;
-        for (int c = 0; c < a.k; ++c) rank += key[c] < kb;
-        out[rank] = (uint8_t)b;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Point access.
-__device__ __forceinline__ void load_point(const Points &P, int64_t idx, float &x,
-                                           float &y, float &z, uint32_t &cnt) {
+// Point of a state: packed key and weight.
+__device__ __forceinline__ void load_point(const Points &P, int64_t idx, uint32_t &key,
+                                           uint32_t &cnt) {
     if (P.is_pixels) {
         const uint8_t *px = P.rgb + idx * 3;
-        x = (float)px[0];
-        y = (float)px[1];
-        z = (float)px[2];
+        key = ((uint32_t)px[0] << 16) | ((uint32_t)px[1] << 8) | (uint32_t)px[2];
         cnt = 1u;
     } else {
-        unpack_key(P.colors[idx], x, y, z);
+        key = P.colors[idx];
         cnt = P.counts[idx];
     }
 }
 
-// Full search over all K centers with the same tie key.
-__device__ __forceinline__ int full_scan(float x, float y, float z, int p, int K,
-                                         const float4 *cen, float &best_d, uint32_t &ev) {
-    const float4 cp = cen[p];
-    float bd = sq_dist(x, y, z, cp.x, cp.y, cp.z);
-    int best = p;
-    for (int t = 0; t < K; ++t) {
-        if (t == p) continue;
-        const float4 ct = cen[t];
-        const float d = sq_dist(x, y, z, ct.x, ct.y, ct.z);
-        if (better_center(d, bd, t, best, p)) {
-            bd = d;
-            best = t;
+// Add one point's weighted color to the block's LDS sums.  All lanes of the
+// wave must call it; runs of equal centers are pre-summed first.
+template <bool PACKED>
+__device__ __forceinline__ void accumulate(unsigned long long *acc, int best, bool valid,
+                                           uint32_t key, uint32_t cnt) {
+    const unsigned long long c = valid ? (unsigned long long)cnt : 0ull;
+    const unsigned long long r = (key >> 16) & 0xFFu, g = (key >> 8) & 0xFFu, b = key & 0xFFu;
+    unsigned long long v0, v1, v2 = 0, v3 = 0;
+    if (PACKED) {
+        v0 = c * r | ((c * g) << 32);
+        v1 = c * b | (c << 32);
+    } else {
+        v0 = c * r;
+        v1 = c * g;
+        v2 = c * b;
+        v3 = c;
+    }
+    const int k = valid ? best : -1;
+    const int head = run_head(k);
+    wave_seg_sum2(head, v0, v1);
+    if (!PACKED) wave_seg_sum2(head, v2, v3);
+    if (run_tail(k, valid)) {
+        if (PACKED) {
+            atomicAdd(&acc[best * 2 + 0], v0);
+            atomicAdd(&acc[best * 2 + 1], v1);
+        } else {
+            atomicAdd(&acc[best * 4 + 0], v0);
+            atomicAdd(&acc[best * 4 + 1], v1);
+            atomicAdd(&acc[best * 4 + 2], v2);
+            atomicAdd(&acc[best * 4 + 3], v3);
         }
     }
-    ev += (uint32_t)K;
-    best_d = bd;
-    return best;
 }
 
-// Search over this block's contiguous chunk of points, accumulation into
-// LDS, flush of the block's totals and partials.
-template <bool FULL>
-__device__ void search_phase(const IterArgs &a, int i, const float4 *cen,
-                             unsigned long long *acc, double *dscr,
-                             unsigned long long *uscr) {
+// One launch = one iteration (see the file comment).
+template <bool PACKED, bool FULL>
+__global__ __launch_bounds__(kSearchThreads) void step_kernel(IterArgs a, int i) {
+    __shared__ float4 cen[kMaxK];
+    __shared__ unsigned long long acc[kMaxK * 4];
+    __shared__ RowLists L;
+    __shared__ double dscr[kSearchThreads / 64];
+    __shared__ unsigned long long uscr[kSearchThreads / 64];
+    constexpr int NT = kSearchThreads;
+    constexpr int NACC = PACKED ? 2 : 4;
     const int tid = threadIdx.x;
     const int g = blockIdx.x;
-    for (int c = tid; c < a.k * 4; c += kSearchThreads) acc[c] = 0ull;
-    __syncthreads();
     const int64_t n = a.pts.n;
     int64_t chunk = (n + a.grid - 1) / a.grid;
     chunk = (chunk + 63) / 64 * 64;
     const int64_t start = (int64_t)g * chunk;
     const int64_t end = (start + chunk) < n ? (start + chunk) : n;
+
+    // Prefetch the first pass's points while the update loads are in flight.
+    uint32_t key[kCpt], cnt[kCpt];
+    int pm[kCpt];
+#pragma unroll
+    for (int r = 0; r < kCpt; ++r) {
+        const int64_t idx = start + r * NT + tid;
+        key[r] = 0u;
+        cnt[r] = 0u;
+        pm[r] = 0;
+        if (idx < end) {
+            load_point(a.pts, idx, key[r], cnt[r]);
+            pm[r] = a.sv.m[idx];
+        }
+    }
+    const Record rec = update_phase<NT, PACKED>(a, i, cen, g == 0, dscr, uscr);
+    if (rec.converged) return;
+    if (g == 0) {
+        unsigned long long *Tn = a.sv.totals + (size_t)((i + 1) % 3) * kMaxK * 4;
+        for (int c = tid; c < kMaxK * 4; c += NT) Tn[c] = 0ull;
+    }
+    for (int c = tid; c < a.k * NACC; c += NT) acc[c] = 0ull;
+
     double sse = 0.0;
     uint32_t ev = 0;
-    for (int64_t idx = start + tid; idx < end; idx += kSearchThreads) {
-        float x, y, z;
-        uint32_t cnt;
-        load_point(a.pts, idx, x, y, z, cnt);
-        const int p = a.sv.m[idx];
-        float bd;
-        int best;
-        if (FULL)
-            best = full_scan(x, y, z, p, a.k, cen, bd, ev);
-        else
-            best = sm_scan(x, y, z, p, a.k, cen, a.sv.rows, bd, ev);
-        a.sv.m[idx] = (uint8_t)best;
-        sse += (double)cnt * (double)bd;
-        const unsigned long long c64 = cnt;
-        atomicAdd(&acc[best * 4 + 0], c64 * (unsigned long long)x);
-        atomicAdd(&acc[best * 4 + 1], c64 * (unsigned long long)y);
-        atomicAdd(&acc[best * 4 + 2], c64 * (unsigned long long)z);
-        atomicAdd(&acc[best * 4 + 3], c64);
+    for (int64_t base = start; base < end; base += kPass) {
+        if (base != start) {
+#pragma unroll
+            for (int r = 0; r < kCpt; ++r) {
+                const int64_t idx = base + r * NT + tid;
+                if (idx < end) {
+                    load_point(a.pts, idx, key[r], cnt[r]);
+                    pm[r] = a.sv.m[idx];
+                }
+            }
+        }
+        bool lists_ok = false;
+        if (!FULL) {
+            reset_row_lists(L, a.k);
+            __syncthreads();
+            // Largest break threshold of the pass's points, per row.
+#pragma unroll
+            for (int r = 0; r < kCpt; ++r) {
+                if (base + r * NT >= end) break;  // block-uniform
+                const bool valid = base + r * NT + tid < end;
+                float x, y, z;
+                unpack_key(key[r], x, y, z);
+                const float4 cp = cen[pm[r]];
+                add_threshold(L, valid, pm[r], sq_dist(x, y, z, cp.x, cp.y, cp.z));
+            }
+            __syncthreads();
+            build_row_lists<NT>(L, cen, a.k);
+            lists_ok = !L.overflow;
+        } else {
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < kCpt; ++r) {
+            if (base + r * NT >= end) break;  // block-uniform
+            const int64_t idx = base + r * NT + tid;
+            const bool valid = idx < end;
+            float x, y, z;
+            unpack_key(key[r], x, y, z);
+            float bd = 0.f;
+            int best = 0;
+            if (valid) {
+                if (lists_ok)
+                    best = sm_scan_lists(x, y, z, pm[r], cen, L, bd, ev);
+                else
+                    best = full_scan(x, y, z, pm[r], a.k, cen, bd, ev);
+                a.sv.m[idx] = (uint8_t)best;
+                sse += (double)cnt[r] * (double)bd;
+            }
+            accumulate<PACKED>(acc, best, valid, key[r], cnt[r]);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     unsigned long long *T = a.sv.totals + (size_t)(i % 3) * kMaxK * 4;
-    for (int c = tid; c < a.k * 4; c += kSearchThreads) {
+    for (int c = tid; c < a.k * NACC; c += NT) {
         const unsigned long long v = acc[c];
-        if (v != 0ull) atomicAdd(&T[c], v);
+        if (v != 0ull) atomicAdd(&T[(c / NACC) * 4 + (c % NACC)], v);
     }
-    const double s = block_sum_double<kSearchThreads>(sse, dscr);
-    const unsigned long long e = block_sum_u64<kSearchThreads>((unsigned long long)ev, uscr);
+    const double s = block_sum_f64<NT>(sse, dscr);
+    const unsigned long long e = block_sum_u64<NT>((unsigned long long)ev, uscr);
     if (tid == 0) {
         a.sv.sse_part[(size_t)(i & 1) * kMaxGrid + g] = s;
         a.sv.eval_part[(size_t)(i & 1) * kMaxGrid + g] = e;
     }
 }
 
-// Sort-means search of step i (after rows_kernel of step i).
-__global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int i) {
-    __shared__ float4 cen[kMaxK];
-    __shared__ unsigned long long acc[kMaxK * 4];
-    __shared__ double dscr[kSearchThreads / 64];
-    __shared__ unsigned long long uscr[kSearchThreads / 64];
-    const int tid = threadIdx.x;
-    const Record r = a.sv.hdr->rec[(i + 1) & 1];
-    if (r.converged) return;
-    const float4 *pal = a.sv.pal + (size_t)((i + 1) & 1) * kMaxK;
-    for (int c = tid; c < a.k; c += kSearchThreads) cen[c] = pal[c];
-    __syncthreads();
-    search_phase<false>(a, i, cen, acc, dscr, uscr);
-}
-
-// Full-search comparator: update of step i-1 fused with the search of step i.
-__global__ __launch_bounds__(kSearchThreads) void full_step_kernel(IterArgs a, int i) {
-    __shared__ float4 cen[kMaxK];
-    __shared__ unsigned long long acc[kMaxK * 4];
-    __shared__ double dscr[kSearchThreads / 64];
-    __shared__ unsigned long long uscr[kSearchThreads / 64];
-    const int tid = threadIdx.x;
-    const Record r = update_phase<kSearchThreads>(a, i, cen, blockIdx.x == 0, dscr, uscr);
-    if (r.converged) return;
-    if (blockIdx.x == 0) {
-        unsigned long long *T = a.sv.totals + (size_t)((i + 1) % 3) * kMaxK * 4;
-        for (int c = tid; c < kMaxK * 4; c += kSearchThreads) T[c] = 0ull;
-    }
-    search_phase<true>(a, i, cen, acc, dscr, uscr);
-}
-
 // Final update after the last step of a call (one block).  Publishes the
 // palette and record to slot 0 and clears totals[0] for the next call.
+template <bool PACKED>
 __global__ __launch_bounds__(kRowThreads) void final_kernel(IterArgs a, int i) {
     __shared__ float4 cen[kMaxK];
     __shared__ double dscr[4];
     __shared__ unsigned long long uscr[4];
     const int tid = threadIdx.x;
-    const Record r = update_phase<kRowThreads>(a, i, cen, true, dscr, uscr);
+    const Record r = update_phase<kRowThreads, PACKED>(a, i, cen, true, dscr, uscr);
     __syncthreads();
     for (int c = tid; c < a.k; c += kRowThreads) a.sv.pal[c] = cen[c];
     unsigned long long *T0 = a.sv.totals;
@@ -346,16 +378,6 @@ __global__ void gather_palette_kernel(const uint32_t *__restrict__ colors, int64
 
 using namespace wsm;
 
-extern "C" int wsm_gather_palette(const uint32_t *colors, int64_t n_colors,
-                                  const int32_t *indices, int k, float *palette,
-                                  hipStream_t stream) {
-    if (!colors || !indices || !palette || n_colors < 1 || k < 1 || k > kMaxK) return WSM_EINVAL;
-    (void)hipGetLastError();
-    gather_palette_kernel<<<dim3(1), dim3(kMaxK), 0, stream>>>(colors, n_colors, indices, k,
-                                                               palette);
-    return hipGetLastError() == hipSuccess ? WSM_OK : WSM_EHIP;
-}
-
 // ---------------------------------------------------------------------------
 // Host side.
 
@@ -387,14 +409,18 @@ static int init_common(wsm_problem *prob, void *state, size_t state_bytes, int p
     int cus = 0;
     int rc = device_cus(&cus);
     if (rc != WSM_OK) return rc;
-    int grid = cus;
+    // One block per CU, fewer for small tables, more when a block would
+    // otherwise need more than two passes.
+    int64_t grid = cus;
+    const int64_t by_size = (n_points + kSearchThreads - 1) / kSearchThreads;
+    if (by_size < grid) grid = by_size;
+    const int64_t by_pass = (n_points + 2 * (int64_t)kPass - 1) / (2 * (int64_t)kPass);
+    if (by_pass > grid) grid = by_pass;
     if (grid > kMaxGrid) grid = kMaxGrid;
-    const int64_t need = (n_points + kSearchThreads - 1) / kSearchThreads;
-    if (need < grid) grid = (int)need;
     if (grid < 1) grid = 1;
     StateView sv = make_view(state);
     (void)hipGetLastError();
-    init_state_kernel<<<dim3(256), dim3(256), 0, stream>>>(sv, k, points, grid, n_points,
+    init_state_kernel<<<dim3(256), dim3(256), 0, stream>>>(sv, k, points, (int)grid, n_points,
                                                           n_pixels, init_palette);
     if (hipGetLastError() != hipSuccess) return WSM_EHIP;
     prob->k = k;
@@ -407,7 +433,7 @@ static int init_common(wsm_problem *prob, void *state, size_t state_bytes, int p
     prob->counts = counts;
     prob->rgb = rgb;
     prob->magic = kMagic;
-    prob->grid = grid;
+    prob->grid = (int)grid;
     return WSM_OK;
 }
 
@@ -433,6 +459,7 @@ static int check_problem(const wsm_problem *prob) {
     if (!prob || prob->magic != kMagic || !prob->state) return WSM_EINVAL;
     if (prob->k < 1 || prob->k > kMaxK || prob->n_points < 1) return WSM_EINVAL;
     if (prob->grid < 1 || prob->grid > kMaxGrid) return WSM_EINVAL;
+    if (prob->n_pixels < 1 || prob->n_pixels > (int64_t)0xFFFFFFFFll) return WSM_EINVAL;
     if (prob->points == WSM_POINTS_COLORS) {
         if (!prob->colors || !prob->counts) return WSM_EINVAL;
     } else if (prob->points == WSM_POINTS_PIXELS) {
@@ -444,6 +471,8 @@ static int check_problem(const wsm_problem *prob) {
     return WSM_OK;
 }
 
+int wsm_internal_check_problem(const wsm_problem *prob) { return check_problem(prob); }
+
 static IterArgs make_args(const wsm_problem *prob, double eps) {
     IterArgs a;
     a.sv = make_view(prob->state);
@@ -454,6 +483,7 @@ static IterArgs make_args(const wsm_problem *prob, double eps) {
     a.pts.is_pixels = prob->points == WSM_POINTS_PIXELS ? 1 : 0;
     a.k = prob->k;
     a.grid = prob->grid;
+    a.n_pixels = prob->n_pixels;
     a.eps = eps;
     return a;
 }
@@ -466,39 +496,44 @@ static int check_iter_args(const wsm_problem *prob, int max_iters, double eps) {
     return WSM_OK;
 }
 
-extern "C" int wsm_iterate(const wsm_problem *prob, int max_iters, double eps,
-                           hipStream_t stream) {
+// Exact packing of the four sums into two 64-bit words needs 255 N < 2^32.
+static bool packed_sums(const wsm_problem *prob) {
+    return (unsigned long long)prob->n_pixels * 255ull < (1ull << 32);
+}
+
+template <bool PACKED>
+static int launch_steps(const IterArgs &a, int max_iters, bool full, hipStream_t stream) {
+    const int kind = full ? WSM_KERNEL_FULL_STEP : WSM_KERNEL_SEARCH;
+    for (int i = 0; i < max_iters; ++i) {
+        timing_before(kind, stream);
+        if (full)
+            step_kernel<PACKED, true><<<dim3(a.grid), dim3(kSearchThreads), 0, stream>>>(a, i);
+        else
+            step_kernel<PACKED, false><<<dim3(a.grid), dim3(kSearchThreads), 0, stream>>>(a, i);
+        timing_after(kind, stream);
+    }
+    final_kernel<PACKED><<<dim3(1), dim3(kRowThreads), 0, stream>>>(a, max_iters);
+    return hipGetLastError() == hipSuccess ? WSM_OK : WSM_EHIP;
+}
+
+static int iterate_impl(const wsm_problem *prob, int max_iters, double eps, bool full,
+                        hipStream_t stream) {
     int rc = check_iter_args(prob, max_iters, eps);
     if (rc != WSM_OK) return rc;
     const IterArgs a = make_args(prob, eps);
     (void)hipGetLastError();
-    for (int i = 0; i < max_iters; ++i) {
-        timing_before(WSM_KERNEL_ROWS, stream);
-        rows_kernel<<<dim3(a.k), dim3(kRowThreads), 0, stream>>>(a, i, 0);
-        timing_after(WSM_KERNEL_ROWS, stream);
-        timing_before(WSM_KERNEL_SEARCH, stream);
-        search_kernel<<<dim3(a.grid), dim3(kSearchThreads), 0, stream>>>(a, i);
-        timing_after(WSM_KERNEL_SEARCH, stream);
-    }
-    final_kernel<<<dim3(1), dim3(kRowThreads), 0, stream>>>(a, max_iters);
-    if (hipGetLastError() != hipSuccess) return WSM_EHIP;
-    return WSM_OK;
+    return packed_sums(prob) ? launch_steps<true>(a, max_iters, full, stream)
+                             : launch_steps<false>(a, max_iters, full, stream);
+}
+
+extern "C" int wsm_iterate(const wsm_problem *prob, int max_iters, double eps,
+                           hipStream_t stream) {
+    return iterate_impl(prob, max_iters, eps, false, stream);
 }
 
 extern "C" int wsm_iterate_full(const wsm_problem *prob, int max_iters, double eps,
                                 hipStream_t stream) {
-    int rc = check_iter_args(prob, max_iters, eps);
-    if (rc != WSM_OK) return rc;
-    const IterArgs a = make_args(prob, eps);
-    (void)hipGetLastError();
-    for (int i = 0; i < max_iters; ++i) {
-        timing_before(WSM_KERNEL_FULL_STEP, stream);
-        full_step_kernel<<<dim3(a.grid), dim3(kSearchThreads), 0, stream>>>(a, i);
-        timing_after(WSM_KERNEL_FULL_STEP, stream);
-    }
-    final_kernel<<<dim3(1), dim3(kRowThreads), 0, stream>>>(a, max_iters);
-    if (hipGetLastError() != hipSuccess) return WSM_EHIP;
-    return WSM_OK;
+    return iterate_impl(prob, max_iters, eps, true, stream);
 }
 
 extern "C" int wsm_state_views(const wsm_problem *prob, wsm_views *views) {
@@ -514,9 +549,12 @@ extern "C" int wsm_state_views(const wsm_problem *prob, wsm_views *views) {
     return WSM_OK;
 }
 
-// Launch helper used by the pixel map: M for the public palette.
-int wsm_internal_rows_for_map(const wsm_problem *prob, hipStream_t stream) {
-    const IterArgs a = make_args(prob, 0.0);
-    rows_kernel<<<dim3(a.k), dim3(kRowThreads), 0, stream>>>(a, 0, 1);
+extern "C" int wsm_gather_palette(const uint32_t *colors, int64_t n_colors,
+                                  const int32_t *indices, int k, float *palette,
+                                  hipStream_t stream) {
+    if (!colors || !indices || !palette || n_colors < 1 || k < 1 || k > kMaxK) return WSM_EINVAL;
+    (void)hipGetLastError();
+    gather_palette_kernel<<<dim3(1), dim3(kMaxK), 0, stream>>>(colors, n_colors, indices, k,
+                                                               palette);
     return hipGetLastError() == hipSuccess ? WSM_OK : WSM_EHIP;
 }

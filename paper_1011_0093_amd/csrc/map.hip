@@ -1,46 +1,79 @@
 // Pixel mapping (Sec. 1: the second phase of color quantization) and the MSE
 // of Sec. 3.1, on gfx950.
 //
-//   rows    M for the final palette (the rows kernel of the iteration, in
-//           map mode).
-//   assign  one lane per unique color: a sort-means scan against the final
-//           palette from the color's last membership gives its palette
-//           index, scattered into a 2^24-entry byte table at the color's key;
-//           count * distance is summed per block for the MSE.
+//   assign  a sort-means scan of every unique color against the final palette,
+//           starting from the color's last membership, over the truncated
+//           sorted rows each block builds in LDS (sm_block.h).  The palette
+//           index is scattered into a 2^24-entry byte table at the color's
+//           key; count * distance is summed per block for the MSE.
 //   gather  16 pixels per lane: three 16-byte loads, 16 table lookups, one
 //           16-byte store of indices (and 48 bytes of rounded palette colors
 //           when asked for).  Block 0 also sums the MSE partials.
-#include "wsm_internal.h"
+#include "sm_block.h"
 
-int wsm_internal_rows_for_map(const wsm_problem *prob, hipStream_t stream);
+int wsm_internal_check_problem(const wsm_problem *prob);
 
 namespace wsm {
 
 constexpr int kMapThreads = 256;
 constexpr int kGatherPpt = 16;
 
-__global__ __launch_bounds__(kMapThreads) void map_assign_kernel(
+__global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
     StateView sv, const uint32_t *__restrict__ colors, const uint32_t *__restrict__ counts,
-    int64_t n, int K, uint8_t *__restrict__ lut) {
+    int64_t n, int K, int64_t chunk, uint8_t *__restrict__ lut) {
     __shared__ float4 cen[kMaxK];
-    __shared__ double dscr[kMapThreads / 64];
+    __shared__ RowLists L;
+    __shared__ double dscr[kSearchThreads / 64];
+    constexpr int NT = kSearchThreads;
     const int tid = threadIdx.x;
-    for (int c = tid; c < K; c += kMapThreads) cen[c] = sv.pal[c];
-    __syncthreads();
+    const int64_t start = (int64_t)blockIdx.x * chunk;
+    const int64_t end = (start + chunk) < n ? (start + chunk) : n;
+    for (int c = tid; c < K; c += NT) cen[c] = sv.pal[c];
     double acc = 0.0;
     uint32_t ev = 0;
-    const int64_t stride = (int64_t)gridDim.x * kMapThreads;
-    for (int64_t idx = (int64_t)blockIdx.x * kMapThreads + tid; idx < n; idx += stride) {
-        const uint32_t key = colors[idx];
-        float x, y, z;
-        unpack_key(key, x, y, z);
-        const int p = sv.m[idx];
-        float bd;
-        const int best = sm_scan(x, y, z, p, K, cen, sv.rows, bd, ev);
-        lut[key] = (uint8_t)best;
-        acc += (double)counts[idx] * (double)bd;
+    for (int64_t base = start; base < end; base += kPass) {
+        uint32_t key[kCpt];
+        int pm[kCpt];
+#pragma unroll
+        for (int r = 0; r < kCpt; ++r) {
+            const int64_t idx = base + r * NT + tid;
+            key[r] = 0u;
+            pm[r] = 0;
+            if (idx < end) {
+                key[r] = colors[idx];
+                pm[r] = sv.m[idx];
+            }
+        }
+        reset_row_lists(L, K);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kCpt; ++r) {
+            if (base + r * NT >= end) break;  // block-uniform
+            const bool valid = base + r * NT + tid < end;
+            float x, y, z;
+            unpack_key(key[r], x, y, z);
+            const float4 cp = cen[pm[r]];
+            add_threshold(L, valid, pm[r], sq_dist(x, y, z, cp.x, cp.y, cp.z));
+        }
+        __syncthreads();
+        build_row_lists<NT>(L, cen, K);
+        const bool lists_ok = !L.overflow;
+#pragma unroll
+        for (int r = 0; r < kCpt; ++r) {
+            const int64_t idx = base + r * NT + tid;
+            if (idx < end) {
+                float x, y, z;
+                unpack_key(key[r], x, y, z);
+                float bd;
+                const int best = lists_ok ? sm_scan_lists(x, y, z, pm[r], cen, L, bd, ev)
+                                          : full_scan(x, y, z, pm[r], K, cen, bd, ev);
+                lut[key[r]] = (uint8_t)best;
+                acc += (double)counts[idx] * (double)bd;
+            }
+        }
+        __syncthreads();
     }
-    const double s = block_sum_double<kMapThreads>(acc, dscr);
+    const double s = block_sum_f64<NT>(acc, dscr);
     if (tid == 0) sv.map_part[blockIdx.x] = s;
 }
 
@@ -129,21 +162,22 @@ using namespace wsm;
 extern "C" int wsm_map_pixels(const wsm_problem *prob, const uint8_t *rgb, int64_t n_pixels,
                               uint8_t *lut, uint8_t *index_out, uint8_t *rgb_out,
                               double *mse_out, hipStream_t stream) {
-    if (!prob || prob->magic != kMagic || !prob->state) return WSM_EINVAL;
-    if (prob->points != WSM_POINTS_COLORS || !prob->colors || !prob->counts) return WSM_EINVAL;
-    if (prob->k < 1 || prob->k > kMaxK || prob->n_points < 1) return WSM_EINVAL;
-    if (prob->state_bytes < state_bytes_for(prob->n_points)) return WSM_ENOSPC;
+    const int rc = wsm_internal_check_problem(prob);
+    if (rc != WSM_OK) return rc;
+    if (prob->points != WSM_POINTS_COLORS) return WSM_EINVAL;
     if (!rgb || !lut || !index_out) return WSM_EINVAL;
     if (n_pixels < 1 || n_pixels != prob->n_pixels) return WSM_EINVAL;
     StateView sv = make_view(prob->state);
     (void)hipGetLastError();
-    int rc = wsm_internal_rows_for_map(prob, stream);
-    if (rc != WSM_OK) return rc;
-    int64_t nb = (prob->n_points + kMapThreads - 1) / kMapThreads;
+    // about one point per thread; at most kMaxGrid blocks
+    int64_t nb = (prob->n_points + kSearchThreads - 1) / kSearchThreads;
     if (nb > kMaxGrid) nb = kMaxGrid;
+    int64_t chunk = (prob->n_points + nb - 1) / nb;
+    chunk = (chunk + 63) / 64 * 64;
+    nb = (prob->n_points + chunk - 1) / chunk;
     timing_before(WSM_KERNEL_MAP_ASSIGN, stream);
-    map_assign_kernel<<<dim3((unsigned)nb), dim3(kMapThreads), 0, stream>>>(
-        sv, prob->colors, prob->counts, prob->n_points, prob->k, lut);
+    map_assign_kernel<<<dim3((unsigned)nb), dim3(kSearchThreads), 0, stream>>>(
+        sv, prob->colors, prob->counts, prob->n_points, prob->k, chunk, lut);
     timing_after(WSM_KERNEL_MAP_ASSIGN, stream);
     if (hipGetLastError() != hipSuccess) return WSM_EHIP;
     const int64_t per_block = (int64_t)kMapThreads * kGatherPpt;

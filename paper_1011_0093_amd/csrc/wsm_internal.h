@@ -62,8 +62,7 @@ constexpr size_t kOffSsePart = kOffTotals + 3 * kMaxK * 4 * 8;        // double[
 constexpr size_t kOffEvalPart = kOffSsePart + 2 * kMaxGrid * 8;       // u64[2][kMaxGrid]
 constexpr size_t kOffSseHist = kOffEvalPart + 2 * kMaxGrid * 8;       // double[kHistory]
 constexpr size_t kOffEvalHist = kOffSseHist + kHistory * 8;           // int64[kHistory]
-constexpr size_t kOffRows = kOffEvalHist + kHistory * 8;              // u8[256][256]
-constexpr size_t kOffMapPart = kOffRows + kMaxK * kMaxK;              // double[kMaxGrid]
+constexpr size_t kOffMapPart = kOffEvalHist + kHistory * 8;           // double[kMaxGrid]
 constexpr size_t kOffMembership = align_up(kOffMapPart + kMaxGrid * 8, 256);
 
 inline size_t state_bytes_for(int64_t n_points) {
@@ -79,7 +78,6 @@ struct StateView {
     unsigned long long *eval_part;  // [2][kMaxGrid]
     double *sse_hist;
     long long *eval_hist;
-    uint8_t *rows;        // [256][256]
     double *map_part;     // [kMaxGrid]
     uint8_t *m;           // [n_points]
 };
@@ -94,7 +92,6 @@ inline StateView make_view(void *state) {
     v.eval_part = (unsigned long long *)(b + kOffEvalPart);
     v.sse_hist = (double *)(b + kOffSseHist);
     v.eval_hist = (long long *)(b + kOffEvalHist);
-    v.rows = (uint8_t *)(b + kOffRows);
     v.map_part = (double *)(b + kOffMapPart);
     v.m = (uint8_t *)(b + kOffMembership);
     return v;
@@ -142,84 +139,6 @@ __device__ __forceinline__ void unpack_key(uint32_t key, float &r, float &g,
     r = (float)((key >> 16) & 0xFFu);
     g = (float)((key >> 8) & 0xFFu);
     b = (float)(key & 0xFFu);
-}
-
-// Sort-means scan of row p of M (Alg. 2 inner loop).  Returns the best
-// center and its distance; `ev` counts point-center distances evaluated.
-__device__ __forceinline__ int sm_scan(float x, float y, float z, int p, int K,
-                                       const float4 *cen, const uint8_t *rows,
-                                       float &best_d, uint32_t &ev) {
-    const float4 cp = cen[p];
-    const float prev = sq_dist(x, y, z, cp.x, cp.y, cp.z);
-    const float thr = prev * kBreakScale;
-    float bd = prev;
-    int best = p;
-    ev += 1;
-    const uint32_t *row = (const uint32_t *)(rows + (size_t)p * kMaxK);
-    bool active = K > 1;
-    for (int q = 0; active && 4 * q < K; ++q) {
-        const uint32_t w = row[q];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int j = 4 * q + u;
-            if (active && j >= 1) {
-                if (j >= K) {
-                    active = false;
-                } else {
-                    const int t = (int)((w >> (8 * u)) & 0xFFu);
-                    const float4 ct = cen[t];
-                    const float dpt = sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z);
-                    if (dpt >= thr) {
-                        active = false;
-                    } else {
-                        const float d = sq_dist(x, y, z, ct.x, ct.y, ct.z);
-                        ev += 1;
-                        if (better_center(d, bd, t, best, p)) {
-                            bd = d;
-                            best = t;
-                        }
-                    }
-                }
-            }
-        }
-    }
-    best_d = bd;
-    return best;
-}
-
-// Sum of a double over a block in a fixed order (deterministic): each wave
-// reduces by a fixed butterfly, then wave sums are added in wave order.
-template <int NT>
-__device__ __forceinline__ double block_sum_double(double v, double *scratch) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    __syncthreads();
-    if (lane == 0) scratch[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0) {
-        for (int w = 0; w < NT / 64; ++w) s += scratch[w];
-    }
-    __syncthreads();
-    return s;  // valid in thread 0 only
-}
-
-template <int NT>
-__device__ __forceinline__ unsigned long long block_sum_u64(
-    unsigned long long v, unsigned long long *scratch) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    __syncthreads();
-    if (lane == 0) scratch[wave] = v;
-    __syncthreads();
-    unsigned long long s = 0;
-    if (threadIdx.x == 0) {
-        for (int w = 0; w < NT / 64; ++w) s += scratch[w];
-    }
-    __syncthreads();
-    return s;
 }
 
 }  // namespace wsm
