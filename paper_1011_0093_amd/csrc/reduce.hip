@@ -3,17 +3,20 @@
 // emitted in ascending key order.
 //
 // Two kernels, both staging their hot data in LDS:
-//   partition  one block per tile of T pixels.  Each pixel's key
+//   partition  one block per tile of up to 16384 pixels.  Each pixel's key
 //              R<<16 | G<<8 | B is split into a slice (top 9 bits, 512
 //              slices) and a 15-bit low key.  An LDS histogram of the tile's
 //              slices gives every pixel a rank; the low keys are written out
 //              grouped by slice (a tile-local counting sort), 2 bytes per
-//              pixel, together with a (offset, count) word per (slice, tile).
-//   compact    one block per slice.  A 2^15-bin LDS histogram counts the
-//              slice's low keys from every tile; the non-empty bins are
-//              compacted in ascending order, and the slice's place in the
-//              output is found with a decoupled look-back over the slices
-//              before it.
+//              pixel with 16-byte stores, together with an (offset, count)
+//              word per (slice, tile).
+//   compact    one block per slice.  Sixteen lanes read one tile's segment
+//              of the slice together with 16-byte loads, several segments'
+//              loads in flight at once, into a 2^15-bin LDS histogram; the non-empty bins are compacted in
+//              ascending order, and the slice's place in the output comes
+//              from a decoupled look-back over the slices before it, 64
+//              predecessors per step.
+#include "wave_ops.h"
 #include "wsm_internal.h"
 
 namespace wsm {
@@ -21,10 +24,10 @@ namespace wsm {
 constexpr int kSlices = 512;
 constexpr int kSliceBits = 15;
 constexpr int kPartThreads = 1024;
-constexpr int kMaxPpt = 16;                  // pixels per thread (max)
+constexpr int kMaxPpt = 16;                       // pixels per thread (max)
 constexpr int kMaxTile = kPartThreads * kMaxPpt;  // 16384 pixels
 constexpr int kCompactThreads = 1024;
-constexpr int kTileChunk = 2048;             // tiles staged per pass in compact
+constexpr int kGroupsInFlight = 4;                // 16-byte loads in flight per lane
 constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagPrefix = 2ull << 62;
 constexpr unsigned long long kValueMask = (1ull << 62) - 1;
@@ -60,7 +63,7 @@ __global__ __launch_bounds__(kPartThreads) void reduce_partition_kernel(
     int32_t *__restrict__ err_flag) {
     __shared__ uint32_t hist[kSlices];
     __shared__ uint32_t cursor[kSlices];
-    __shared__ uint16_t stage[kMaxTile];
+    __shared__ __align__(16) uint16_t stage[kMaxTile];
     __shared__ uint32_t wave_tot[kPartThreads / 64];
 
     const int tid = threadIdx.x;
@@ -73,9 +76,8 @@ __global__ __launch_bounds__(kPartThreads) void reduce_partition_kernel(
         if (tid == 0) *err_flag = 0;
     }
     for (int s = tid; s < kSlices; s += kPartThreads) hist[s] = 0u;
-    __syncthreads();
 
-    // Load this thread's ppt consecutive pixels and rank each in its slice.
+    // Load this thread's ppt consecutive pixels.
     uint32_t key[kMaxPpt];
     uint32_t rank[kMaxPpt];
     const int first = tid * ppt;
@@ -83,15 +85,15 @@ __global__ __launch_bounds__(kPartThreads) void reduce_partition_kernel(
         // 16 pixels = 48 bytes = three 16-byte loads (tile bases are
         // 48-byte multiples and the image base is 16-byte aligned).
         const uint4 *src = (const uint4 *)(rgb + (base + first) * 3);
-        uint4 q0 = src[0], q1 = src[1], q2 = src[2];
-        uint32_t w[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y,
-                          q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+        const uint4 q0 = src[0], q1 = src[1], q2 = src[2];
+        const uint32_t w[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y,
+                                q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
 #pragma unroll
         for (int j = 0; j < kMaxPpt; ++j) {
             const int byte = 3 * j;
-            uint32_t r = (w[byte >> 2] >> (8 * (byte & 3))) & 0xFFu;
-            uint32_t g = (w[(byte + 1) >> 2] >> (8 * ((byte + 1) & 3))) & 0xFFu;
-            uint32_t bl = (w[(byte + 2) >> 2] >> (8 * ((byte + 2) & 3))) & 0xFFu;
+            const uint32_t r = (w[byte >> 2] >> (8 * (byte & 3))) & 0xFFu;
+            const uint32_t g = (w[(byte + 1) >> 2] >> (8 * ((byte + 1) & 3))) & 0xFFu;
+            const uint32_t bl = (w[(byte + 2) >> 2] >> (8 * ((byte + 2) & 3))) & 0xFFu;
             key[j] = (r << 16) | (g << 8) | bl;
         }
     } else {
@@ -105,6 +107,8 @@ __global__ __launch_bounds__(kPartThreads) void reduce_partition_kernel(
             }
         }
     }
+    __syncthreads();
+    // Rank every pixel within its slice.
 #pragma unroll
     for (int j = 0; j < kMaxPpt; ++j) {
         rank[j] = 0u;
@@ -113,18 +117,14 @@ __global__ __launch_bounds__(kPartThreads) void reduce_partition_kernel(
     __syncthreads();
 
     // Exclusive scan of the 512 slice counts (2 per thread in the first 256).
+    const int lane = tid & 63, wave = tid >> 6;
     uint32_t a0 = 0, a1 = 0;
     if (tid < kSlices / 2) {
         a0 = hist[2 * tid];
         a1 = hist[2 * tid + 1];
     }
-    uint32_t v = a0 + a1;
-    const int lane = tid & 63, wave = tid >> 6;
-    uint32_t incl = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t o = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += o;
-    }
+    const uint32_t v = a0 + a1;
+    const uint32_t incl = wave_incl_sum(v);
     if (lane == 63) wave_tot[wave] = incl;
     __syncthreads();
     if (tid < kSlices / 2) {
@@ -148,9 +148,12 @@ __global__ __launch_bounds__(kPartThreads) void reduce_partition_kernel(
     }
     __syncthreads();
 
-    // Coalesced write of the tile's grouped low keys.
+    // Write the tile's grouped low keys: 8 keys (16 bytes) per store.
     uint16_t *dst = keys16 + base;
-    for (int q = tid; q < len; q += kPartThreads) dst[q] = stage[q];
+    const int full = len & ~7;
+    for (int q = tid * 8; q < full; q += kPartThreads * 8)
+        *(uint4 *)(dst + q) = *(const uint4 *)(stage + q);
+    for (int q = full + tid; q < len; q += kPartThreads) dst[q] = stage[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -159,9 +162,7 @@ __global__ __launch_bounds__(kCompactThreads) void reduce_compact_kernel(
     int64_t ntiles, int tile, uint32_t *__restrict__ colors,
     uint32_t *__restrict__ counts, unsigned long long *__restrict__ status,
     int32_t *__restrict__ n_unique, int32_t *__restrict__ err_flag) {
-    __shared__ uint32_t hist[1 << kSliceBits];
-    __shared__ uint32_t seg_start[kTileChunk + 1];   // prefix of counts in the chunk
-    __shared__ uint32_t seg_off[kTileChunk];         // offset within the tile
+    __shared__ __align__(16) uint32_t hist[1 << kSliceBits];
     __shared__ uint32_t wave_tot[kCompactThreads / 64];
     __shared__ unsigned long long s_excl;
 
@@ -169,134 +170,139 @@ __global__ __launch_bounds__(kCompactThreads) void reduce_compact_kernel(
     const int lane = tid & 63, wave = tid >> 6;
     const int s = blockIdx.x;
 
-    for (int i = tid; i < (1 << kSliceBits); i += kCompactThreads) hist[i] = 0u;
+    for (int i = tid * 4; i < (1 << kSliceBits); i += kCompactThreads * 4)
+        *(uint4 *)(hist + i) = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
 
-    for (int64_t c0 = 0; c0 < ntiles; c0 += kTileChunk) {
-        const int nt = (int)((ntiles - c0) < kTileChunk ? (ntiles - c0) : kTileChunk);
-        __syncthreads();
-        // Stage the chunk's (offset, count) words and scan the counts.
-        uint32_t cnt0 = 0, cnt1 = 0;
-        const int g0 = 2 * tid, g1 = 2 * tid + 1;
-        if (g0 < nt) {
-            uint32_t w = info[(size_t)s * ntiles + c0 + g0];
-            cnt0 = w & 0xFFFFu;
-            seg_off[g0] = w >> 16;
-        }
-        if (g1 < nt) {
-            uint32_t w = info[(size_t)s * ntiles + c0 + g1];
-            cnt1 = w & 0xFFFFu;
-            seg_off[g1] = w >> 16;
-        }
-        uint32_t v = cnt0 + cnt1, incl = v;
-        for (int off = 1; off < 64; off <<= 1) {
-            uint32_t o = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += o;
-        }
-        if (lane == 63) wave_tot[wave] = incl;
-        __syncthreads();
-        uint32_t wbase = 0;
-        for (int w2 = 0; w2 < wave; ++w2) wbase += wave_tot[w2];
-        const uint32_t excl = wbase + incl - v;
-        if (g0 < nt) seg_start[g0] = excl;
-        if (g1 < nt) seg_start[g1] = excl + cnt0;
-        if (tid == kCompactThreads - 1) seg_start[nt] = wbase + incl;
-        __syncthreads();
-        const uint32_t total = seg_start[nt];
-        // Element e of the chunk lives in the tile g with
-        // seg_start[g] <= e < seg_start[g+1]; each wave finds g for its first
-        // element by bisection and lanes walk forward from there.
-        for (uint32_t e0 = (uint32_t)wave * 64; e0 < total; e0 += kCompactThreads) {
-            int lo = 0, hi = nt - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (seg_start[mid] <= e0) lo = mid; else hi = mid - 1;
+    // Segments are read 16 lanes to a segment (256 contiguous bytes per
+    // quarter-wave and step), four tiles per wave instruction, and
+    // kGroupsInFlight groups of four tiles with their loads in flight together.
+    {
+        const int q = lane >> 4, ql = lane & 15;
+        const int64_t ngroups = (ntiles + 3) / 4;
+        for (int64_t G0 = wave; G0 < ngroups; G0 += (kCompactThreads / 64) * kGroupsInFlight) {
+            size_t s0[kGroupsInFlight], s1[kGroupsInFlight];
+#pragma unroll
+            for (int u = 0; u < kGroupsInFlight; ++u) {
+                const int64_t G = G0 + (int64_t)(kCompactThreads / 64) * u;
+                const int64_t g = G * 4 + q;
+                const uint32_t w = (G < ngroups && g < ntiles) ? info[(size_t)s * ntiles + g] : 0u;
+                s0[u] = (size_t)(g < ntiles ? g : 0) * tile + (w >> 16);
+                s1[u] = s0[u] + (w & 0xFFFFu);
             }
-            const uint32_t e = e0 + lane;
-            if (e < total) {
-                int g = lo;
-                while (seg_start[g + 1] <= e) ++g;
-                const size_t src = (size_t)(c0 + g) * tile + seg_off[g] + (e - seg_start[g]);
-                atomicAdd(&hist[keys16[src]], 1u);
+            for (size_t win = 0;; win += 128) {
+                bool any = false;
+#pragma unroll
+                for (int u = 0; u < kGroupsInFlight; ++u)
+                    any = any || ((s0[u] & ~(size_t)7) + win < s1[u]);
+                if (__ballot(any) == 0ull) break;  // wave-uniform exit
+                uint4 v[kGroupsInFlight];
+                size_t a[kGroupsInFlight];
+#pragma unroll
+                for (int u = 0; u < kGroupsInFlight; ++u) {
+                    a[u] = (s0[u] & ~(size_t)7) + win + 8 * ql;
+                    v[u] = a[u] < s1[u] ? *(const uint4 *)(keys16 + a[u]) : make_uint4(0, 0, 0, 0);
+                }
+#pragma unroll
+                for (int u = 0; u < kGroupsInFlight; ++u) {
+                    const uint32_t wd[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const size_t pos = a[u] + e;
+                        if (pos >= s0[u] && pos < s1[u])
+                            atomicAdd(&hist[(wd[e >> 1] >> (16 * (e & 1))) & 0xFFFFu], 1u);
+                    }
+                }
             }
         }
     }
     __syncthreads();
 
-    // Compaction: thread t owns bins [32 t, 32 t + 32).
-    constexpr int kBinsPerThread = (1 << kSliceBits) / kCompactThreads;
+    // Compaction: wave w owns bins [2048 w, 2048 w + 2048); lane l visits
+    // bins 2048 w + 64 j + l, so LDS reads are conflict-free and the
+    // non-empty bins come out in ascending order with a ballot per step.
+    constexpr int kBinsPerWave = (1 << kSliceBits) / (kCompactThreads / 64);
+    const uint32_t *wb = hist + wave * kBinsPerWave;
     uint32_t mine = 0;
 #pragma unroll 8
-    for (int j = 0; j < kBinsPerThread; ++j) mine += hist[tid * kBinsPerThread + j] != 0u;
-    uint32_t incl = mine;
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t o = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += o;
-    }
-    if (lane == 63) wave_tot[wave] = incl;
+    for (int j = 0; j < kBinsPerWave; j += 64) mine += __popcll(__ballot(wb[j + lane] != 0u));
+    if (lane == 0) wave_tot[wave] = mine;
     __syncthreads();
     uint32_t wbase = 0, slice_total = 0;
     for (int w2 = 0; w2 < kCompactThreads / 64; ++w2) {
         if (w2 < wave) wbase += wave_tot[w2];
         slice_total += wave_tot[w2];
     }
-    const uint32_t local = wbase + incl - mine;
+    const uint32_t local = wbase;
 
-    // Decoupled look-back for the number of unique colors in slices < s.
-    if (tid == 0) {
-        unsigned long long excl = 0;
-        if (s == 0) {
-            __hip_atomic_store(&status[0], kFlagPrefix | slice_total, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(&status[s], kFlagAgg | slice_total, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            int j = s - 1;
-            const unsigned long long t_start = __builtin_amdgcn_s_memrealtime();
-            bool failed = false;
-            while (j >= 0) {
-                unsigned long long w = __hip_atomic_load(&status[j], __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned long long f = w & ~kValueMask;
-                if (f == kFlagPrefix) {
-                    excl += w & kValueMask;
-                    break;
-                } else if (f == kFlagAgg) {
-                    excl += w & kValueMask;
-                    --j;
-                } else {
-                    __builtin_amdgcn_s_sleep(1);
-                    // Bounded wait (2 s at the 100 MHz constant clock).
-                    if (__builtin_amdgcn_s_memrealtime() - t_start > 200000000ull) {
-                        failed = true;
-                        break;
-                    }
-                }
-            }
-            if (failed) {
-                atomicOr(err_flag, 1);
-                excl = 0;
-            }
-            __hip_atomic_store(&status[s], kFlagPrefix | (excl + slice_total),
+    // Decoupled look-back for the number of unique colors in slices < s:
+    // the first wave reads 64 predecessors' words per step.
+    if (wave == 0) {
+        if (lane == 0)
+            __hip_atomic_store(&status[s], (s == 0 ? kFlagPrefix : kFlagAgg) | slice_total,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long excl = 0;
+        bool failed = false;
+        int j = s - 1;
+        const unsigned long long t_start = __builtin_amdgcn_s_memrealtime();
+        while (j >= 0) {
+            // Every lane loads (a clamped index keeps the address valid);
+            // lanes past slice 0 then act as a zero prefix.
+            const int idx = j - lane;
+            const unsigned long long ld = __hip_atomic_load(
+                &status[idx >= 0 ? idx : 0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long wv = idx >= 0 ? ld : kFlagPrefix;
+            const unsigned long long f = wv & ~kValueMask;
+            const unsigned long long pre = __ballot(f == kFlagPrefix);
+            const unsigned long long none = __ballot(f == 0ull);
+            // lanes up to and including the nearest prefix must all be ready
+            const int stop = pre ? __ffsll((long long)pre) - 1 : 63;
+            const unsigned long long need = stop == 63 ? ~0ull : ((2ull << stop) - 1ull);
+            if (none & need) {
+                __builtin_amdgcn_s_sleep(1);
+                // Bounded wait (2 s at the 100 MHz constant clock).
+                if (__builtin_amdgcn_s_memrealtime() - t_start > 200000000ull) {
+                    failed = true;
+                    break;
+                }
+                continue;
+            }
+            const unsigned long long val = (lane <= stop) ? (wv & kValueMask) : 0ull;
+            const unsigned long long tot = wave_sum_u64(val);
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)tot, 63);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(tot >> 32), 63);
+            excl += ((unsigned long long)hi << 32) | lo;
+            if (pre) break;
+            j -= 64;
         }
-        s_excl = excl;
-        if (s == kSlices - 1) *n_unique = (int32_t)(excl + slice_total);
+        if (failed) {
+            if (lane == 0) atomicOr(err_flag, 1);
+            excl = 0;
+        }
+        if (lane == 0) {
+            if (s != 0)
+                __hip_atomic_store(&status[s], kFlagPrefix | (excl + slice_total),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_excl = excl;
+            if (s == kSlices - 1) *n_unique = (int32_t)(excl + slice_total);
+        }
     }
     __syncthreads();
     if (*(volatile int32_t *)err_flag != 0) {
         if (s == kSlices - 1 && tid == 0) *n_unique = -1;
         return;
     }
-    const uint32_t out0 = (uint32_t)s_excl + local;
-    uint32_t o = out0;
-    for (int j = 0; j < kBinsPerThread; ++j) {
-        const int bin = tid * kBinsPerThread + j;
+    uint32_t o = (uint32_t)s_excl + local;
+    for (int j = 0; j < kBinsPerWave; j += 64) {
+        const int bin = wave * kBinsPerWave + j + lane;
         const uint32_t c = hist[bin];
+        const unsigned long long m = __ballot(c != 0u);
         if (c != 0u) {
-            colors[o] = ((uint32_t)s << kSliceBits) | (uint32_t)bin;
-            counts[o] = c;
-            ++o;
+            const uint32_t pos = o + (uint32_t)__popcll(m & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
+            colors[pos] = ((uint32_t)s << kSliceBits) | (uint32_t)bin;
+            counts[pos] = c;
         }
+        o += (uint32_t)__popcll(m);
     }
 }
 
