@@ -1,20 +1,23 @@
-// Iterations of the weighted sort-means loop (Alg. 2) on gfx950: one launch
-// per iteration.
+// Iterations of the weighted sort-means loop (Alg. 2) on gfx950: two
+// launches per iteration (one for the full-search comparator).
 //
-// Every block of step i
-//   1. applies the center update of step i-1 (Alg. 2, last loop:
-//      c_k = sum w x / sum w, from exact integer sums of count * channel),
-//      reduces the SSE partials of step i-1 in a fixed order and evaluates the
-//      Sec. 3.2 stopping rule -- redundantly, so all blocks agree without a
-//      grid-wide barrier; block 0 publishes the palette and the record;
-//   2. searches its contiguous chunk of points: sort-means over the
-//      truncated sorted rows it builds in LDS (sm_block.h), or full search
-//      for the comparator;
-//   3. sums count * (R, G, B, 1) per center: runs of equal centers within a
+// Step i, rows launch (one block per center p):
+//   1. every block applies the center update of step i-1 (Alg. 2, last
+//      loop: c_k = sum w x / sum w, from exact integer sums of
+//      count * channel), reduces the SSE partials of step i-1 in a fixed
+//      order and evaluates the Sec. 3.2 stopping rule -- redundantly, so all
+//      blocks agree without a grid-wide barrier; block 0 publishes the
+//      palette and the record;
+//   2. block p sorts row p of the neighbour matrix M for the new centers
+//      (Sec. 2: the inter-center distances with every row sorted).
+// Step i, search launch (one block per chunk of points):
+//   3. sort-means from each point's previous center over an LDS copy of M;
+//   4. sums count * (R, G, B, 1) per center: runs of equal centers within a
 //      wave are pre-summed with a segmented scan, then added into LDS, and
 //      each block flushes its non-zero sums with 64-bit device atomics (the
 //      second level of the reduction); the block's SSE and evaluation count
 //      go to per-block partials.
+// The full-search comparator does 1, 3 (full search) and 4 in one launch.
 // The sums are exact integers, so the result does not depend on the order
 // of the additions and the pruned search, the full search and k-means on the
 // raw pixels produce bit-identical centers.
@@ -64,7 +67,8 @@ __device__ __forceinline__ void totals_to_center(const unsigned long long *T, in
 }
 
 // Update phase (see the file comment).  Returns the record after the update,
-// identical in every block.
+// identical in every block.  The new centers are in the LDS array cen after
+// the call.
 template <int NT, bool PACKED>
 __device__ Record update_phase(const IterArgs &a, int i, float4 *cen, bool writer,
                                double *dscr, unsigned long long *uscr) {
@@ -186,111 +190,231 @@ __device__ __forceinline__ void accumulate(unsigned long long *acc, int best, bo
     }
 }
 
-// One launch = one iteration (see the file comment).
-template <bool PACKED, bool FULL>
-__global__ __launch_bounds__(kSearchThreads) void step_kernel(IterArgs a, int i) {
-    __shared__ float4 cen[kMaxK];
-    __shared__ unsigned long long acc[kMaxK * 4];
-    __shared__ RowLists L;
-    __shared__ double dscr[kSearchThreads / 64];
-    __shared__ unsigned long long uscr[kSearchThreads / 64];
-    constexpr int NT = kSearchThreads;
-    constexpr int NACC = PACKED ? 2 : 4;
-    const int tid = threadIdx.x;
-    const int g = blockIdx.x;
-    const int64_t n = a.pts.n;
-    int64_t chunk = (n + a.grid - 1) / a.grid;
-    chunk = (chunk + 63) / 64 * 64;
-    const int64_t start = (int64_t)g * chunk;
-    const int64_t end = (start + chunk) < n ? (start + chunk) : n;
+// Points of a block: the 64-point chunks b, b + grid, b + 2 grid, ... of the
+// (key-ordered) table, one chunk per wave and slot, so that every block
+// samples the whole color range and the blocks get similar work.
+__device__ __forceinline__ int64_t block_slots(const IterArgs &a) {
+    const int64_t chunks = (a.pts.n + 63) / 64;
+    const int64_t b = blockIdx.x;
+    return chunks > b ? (chunks - b + a.grid - 1) / a.grid : 0;
+}
 
-    // Prefetch the first pass's points while the update loads are in flight.
-    uint32_t key[kCpt], cnt[kCpt];
-    int pm[kCpt];
+__device__ __forceinline__ int64_t slot_point(const IterArgs &a, int64_t slot) {
+    return ((int64_t)blockIdx.x + slot * a.grid) * 64 + (threadIdx.x & 63);
+}
+
+__device__ __forceinline__ void prefetch_points(const IterArgs &a, uint32_t (&key)[kCpt],
+                                                uint32_t (&cnt)[kCpt], int (&pm)[kCpt]) {
+    const int64_t ns = block_slots(a);
+    const int wave = threadIdx.x >> 6;
 #pragma unroll
     for (int r = 0; r < kCpt; ++r) {
-        const int64_t idx = start + r * NT + tid;
+        const int64_t slot = r * (kSearchThreads / 64) + wave;
+        const int64_t idx = slot_point(a, slot);
         key[r] = 0u;
         cnt[r] = 0u;
         pm[r] = 0;
-        if (idx < end) {
+        if (slot < ns && idx < a.pts.n) {
             load_point(a.pts, idx, key[r], cnt[r]);
             pm[r] = a.sv.m[idx];
         }
     }
-    const Record rec = update_phase<NT, PACKED>(a, i, cen, g == 0, dscr, uscr);
-    if (rec.converged) return;
-    if (g == 0) {
-        unsigned long long *Tn = a.sv.totals + (size_t)((i + 1) % 3) * kMaxK * 4;
-        for (int c = tid; c < kMaxK * 4; c += NT) Tn[c] = 0ull;
-    }
-    for (int c = tid; c < a.k * NACC; c += NT) acc[c] = 0ull;
+}
 
+// Search and accumulation over a block's points (block_slots), in passes of
+// kPass (kCpt points per thread); the first pass's points are already in
+// key/cnt/pm.  Sort-means over the LDS copy Ms of M, or full
+// search for the comparator (Ms unused).  Adds the block's sums into totals
+// slot i % 3 and writes its SSE and evaluation partials.
+template <bool PACKED, bool FULL>
+__device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const uint8_t *Ms,
+                             unsigned long long *acc, double *dscr, unsigned long long *uscr,
+                             uint32_t (&key)[kCpt], uint32_t (&cnt)[kCpt], int (&pm)[kCpt]) {
+    constexpr int NT = kSearchThreads;
+    constexpr int NW = NT / 64;
+    constexpr int NACC = PACKED ? 2 : 4;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int rs = lds_row_stride(a.k);
+    const int64_t ns = block_slots(a);
     double sse = 0.0;
     uint32_t ev = 0;
-    for (int64_t base = start; base < end; base += kPass) {
-        if (base != start) {
+    for (int64_t s0 = 0; s0 < ns; s0 += kCpt * NW) {
+        if (s0 != 0) {
 #pragma unroll
             for (int r = 0; r < kCpt; ++r) {
-                const int64_t idx = base + r * NT + tid;
-                if (idx < end) {
+                const int64_t slot = s0 + r * NW + wave;
+                const int64_t idx = slot_point(a, slot);
+                if (slot < ns && idx < a.pts.n) {
                     load_point(a.pts, idx, key[r], cnt[r]);
                     pm[r] = a.sv.m[idx];
                 }
             }
         }
-        bool lists_ok = false;
-        if (!FULL) {
-            reset_row_lists(L, a.k);
-            __syncthreads();
-            // Largest break threshold of the pass's points, per row.
-#pragma unroll
-            for (int r = 0; r < kCpt; ++r) {
-                if (base + r * NT >= end) break;  // block-uniform
-                const bool valid = base + r * NT + tid < end;
-                float x, y, z;
-                unpack_key(key[r], x, y, z);
-                const float4 cp = cen[pm[r]];
-                add_threshold(L, valid, pm[r], sq_dist(x, y, z, cp.x, cp.y, cp.z));
-            }
-            __syncthreads();
-            build_row_lists<NT>(L, cen, a.k);
-            lists_ok = !L.overflow;
-        } else {
-            __syncthreads();
-        }
 #pragma unroll
         for (int r = 0; r < kCpt; ++r) {
-            if (base + r * NT >= end) break;  // block-uniform
-            const int64_t idx = base + r * NT + tid;
-            const bool valid = idx < end;
+            if (s0 + r * NW >= ns) break;  // block-uniform
+            const int64_t slot = s0 + r * NW + wave;
+            const int64_t idx = slot_point(a, slot);
+            const bool valid = slot < ns && idx < a.pts.n;
             float x, y, z;
             unpack_key(key[r], x, y, z);
             float bd = 0.f;
             int best = 0;
+            if (FULL) {
+                if (valid) best = full_scan(x, y, z, pm[r], a.k, cen, bd, ev);
+            } else {
+                if (valid) best = sm_scan(x, y, z, pm[r], a.k, cen, Ms, rs, bd, ev);
+            }
             if (valid) {
-                if (lists_ok)
-                    best = sm_scan_lists(x, y, z, pm[r], cen, L, bd, ev);
-                else
-                    best = full_scan(x, y, z, pm[r], a.k, cen, bd, ev);
                 a.sv.m[idx] = (uint8_t)best;
                 sse += (double)cnt[r] * (double)bd;
             }
             accumulate<PACKED>(acc, best, valid, key[r], cnt[r]);
         }
-        __syncthreads();
     }
+    __syncthreads();
     unsigned long long *T = a.sv.totals + (size_t)(i % 3) * kMaxK * 4;
     for (int c = tid; c < a.k * NACC; c += NT) {
         const unsigned long long v = acc[c];
         if (v != 0ull) atomicAdd(&T[(c / NACC) * 4 + (c % NACC)], v);
     }
-    const double s = block_sum_f64<NT>(sse, dscr);
-    const unsigned long long e = block_sum_u64<NT>((unsigned long long)ev, uscr);
+    unsigned long long e = ev;
+    block_sum2<NT>(sse, e, dscr, uscr);
     if (tid == 0) {
-        a.sv.sse_part[(size_t)(i & 1) * kMaxGrid + g] = s;
-        a.sv.eval_part[(size_t)(i & 1) * kMaxGrid + g] = e;
+        a.sv.sse_part[(size_t)(i & 1) * kMaxGrid + blockIdx.x] = sse;
+        a.sv.eval_part[(size_t)(i & 1) * kMaxGrid + blockIdx.x] = e;
     }
+}
+
+// Sort-means step i, first launch: the update of step i-1 in every block
+// (see the file comment), then block p sorts row p of M for the new
+// centers.  Block 0 clears the totals slot step i accumulates into.
+template <bool PACKED>
+__global__ __launch_bounds__(kSortThreads) void rows_kernel(IterArgs a, int i) {
+    __shared__ float4 cen[kMaxK];
+    __shared__ __align__(16) unsigned long long keys[kMaxK];
+    __shared__ uint32_t rank[kMaxK];
+    __shared__ double dscr[kSortThreads / 64];
+    __shared__ unsigned long long uscr[kSortThreads / 64];
+    const int p = blockIdx.x;
+    const Record rec = update_phase<kSortThreads, PACKED>(a, i, cen, p == 0, dscr, uscr);
+    if (rec.converged) return;
+    if (p == 0) {
+        unsigned long long *T = a.sv.totals + (size_t)(i % 3) * kMaxK * 4;
+        for (int c = threadIdx.x; c < kMaxK * 4; c += kSortThreads) T[c] = 0ull;
+    }
+    sort_row<kSortThreads>(cen, a.k, p, keys, rank, a.sv.rows + (size_t)p * kRowStride);
+}
+
+// Sort-means step i, second launch: every block copies the centers and M
+// into LDS and searches its chunk.
+template <bool PACKED>
+__global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int i) {
+    __shared__ float4 cen[kMaxK];
+    __shared__ unsigned long long acc[kMaxK * 4];
+    __shared__ __align__(16) uint8_t Ms[kMaxK * kRowStride];
+    __shared__ double dscr[kSearchThreads / 64];
+    __shared__ unsigned long long uscr[kSearchThreads / 64];
+    constexpr int NT = kSearchThreads;
+    constexpr int NACC = PACKED ? 2 : 4;
+    const int tid = threadIdx.x;
+    uint32_t key[kCpt], cnt[kCpt];
+    int pm[kCpt];
+    prefetch_points(a, key, cnt, pm);
+    const Record rec = a.sv.hdr->rec[(i + 1) & 1];
+    if (rec.converged) return;
+    const float4 *pal = a.sv.pal + (size_t)((i + 1) & 1) * kMaxK;
+    for (int c = tid; c < a.k; c += NT) cen[c] = pal[c];
+    load_rows<NT>(a.sv.rows, a.k, Ms);
+    for (int c = tid; c < a.k * NACC; c += NT) acc[c] = 0ull;
+    __syncthreads();
+    search_chunk<PACKED, false>(a, i, cen, Ms, acc, dscr, uscr, key, cnt, pm);
+}
+
+// Rows of M for palette slot 0 of the state (the pixel map's palette).
+__global__ __launch_bounds__(kSortThreads) void palette_rows_kernel(StateView sv, int K) {
+    __shared__ float4 cen[kMaxK];
+    __shared__ __align__(16) unsigned long long keys[kMaxK];
+    __shared__ uint32_t rank[kMaxK];
+    for (int c = threadIdx.x; c < K; c += kSortThreads) cen[c] = sv.pal[c];
+    sort_row<kSortThreads>(cen, K, blockIdx.x, keys, rank, sv.rows + (size_t)blockIdx.x * kRowStride);
+}
+
+// Sort-means step for K <= kFusedMaxK in one launch: every block applies
+// the update as in the rows launch, sorts all K rows of M into LDS itself
+// (thread (p, t) ranks center t in row p) and searches its points.  Totals
+// slots follow the comparator's order: clear (i + 1) % 3, add into i % 3.
+template <bool PACKED>
+__global__ __launch_bounds__(kSearchThreads) void fused_step_kernel(IterArgs a, int i) {
+    __shared__ float4 cen[kMaxK];
+    __shared__ unsigned long long acc[kMaxK * 4];
+    __shared__ __align__(16) unsigned long long keys[kFusedMaxK * kFusedMaxK];
+    __shared__ __align__(16) uint8_t Ms[kFusedMaxK * kFusedMaxK];
+    __shared__ double dscr[kSearchThreads / 64];
+    __shared__ unsigned long long uscr[kSearchThreads / 64];
+    constexpr int NT = kSearchThreads;
+    constexpr int NACC = PACKED ? 2 : 4;
+    static_assert(kFusedMaxK * kFusedMaxK <= NT, "one thread per row entry");
+    const int tid = threadIdx.x;
+    const int K = a.k;
+    uint32_t key[kCpt], cnt[kCpt];
+    int pm[kCpt];
+    prefetch_points(a, key, cnt, pm);
+    const Record rec = update_phase<NT, PACKED>(a, i, cen, blockIdx.x == 0, dscr, uscr);
+    if (rec.converged) return;
+    if (blockIdx.x == 0) {
+        unsigned long long *Tn = a.sv.totals + (size_t)((i + 1) % 3) * kMaxK * 4;
+        for (int c = tid; c < kMaxK * 4; c += NT) Tn[c] = 0ull;
+    }
+    for (int c = tid; c < K * NACC; c += NT) acc[c] = 0ull;
+    const int p = tid / kFusedMaxK, t = tid % kFusedMaxK;
+    const bool entry = p < K && t < K && t != p;
+    unsigned long long kt = ~0ull;
+    if (entry) {
+        const float4 cp = cen[p], ct = cen[t];
+        kt = ((unsigned long long)__float_as_uint(sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z))
+              << 32) | (unsigned)t;
+    }
+    keys[tid] = kt;
+    __syncthreads();
+    if (entry) {
+        const ulonglong2 *k2 = (const ulonglong2 *)(keys + p * kFusedMaxK);
+        uint32_t r = 0;
+#pragma unroll
+        for (int u = 0; u < kFusedMaxK / 2; ++u) {
+            const ulonglong2 v = k2[u];
+            r += (uint32_t)(v.x < kt) + (uint32_t)(v.y < kt);
+        }
+        Ms[p * lds_row_stride(K) + r] = (uint8_t)t;
+    }
+    __syncthreads();
+    search_chunk<PACKED, false>(a, i, cen, Ms, acc, dscr, uscr, key, cnt, pm);
+}
+
+// Full-search comparator: one launch per step, the update applied
+// redundantly by every block as in the sort-means step.
+template <bool PACKED>
+__global__ __launch_bounds__(kSearchThreads) void full_step_kernel(IterArgs a, int i) {
+    __shared__ float4 cen[kMaxK];
+    __shared__ unsigned long long acc[kMaxK * 4];
+    __shared__ double dscr[kSearchThreads / 64];
+    __shared__ unsigned long long uscr[kSearchThreads / 64];
+    constexpr int NT = kSearchThreads;
+    constexpr int NACC = PACKED ? 2 : 4;
+    const int tid = threadIdx.x;
+    uint32_t key[kCpt], cnt[kCpt];
+    int pm[kCpt];
+    prefetch_points(a, key, cnt, pm);
+    const Record rec = update_phase<NT, PACKED>(a, i, cen, blockIdx.x == 0, dscr, uscr);
+    if (rec.converged) return;
+    if (blockIdx.x == 0) {
+        unsigned long long *Tn = a.sv.totals + (size_t)((i + 1) % 3) * kMaxK * 4;
+        for (int c = tid; c < kMaxK * 4; c += NT) Tn[c] = 0ull;
+    }
+    for (int c = tid; c < a.k * NACC; c += NT) acc[c] = 0ull;
+    __syncthreads();
+    search_chunk<PACKED, true>(a, i, cen, nullptr, acc, dscr, uscr, key, cnt, pm);
 }
 
 // Final update after the last step of a call (one block).  Publishes the
@@ -409,10 +533,10 @@ static int init_common(wsm_problem *prob, void *state, size_t state_bytes, int p
     int cus = 0;
     int rc = device_cus(&cus);
     if (rc != WSM_OK) return rc;
-    // One block per CU, fewer for small tables, more when a block would
-    // otherwise need more than two passes.
+    // One block per CU, fewer for small tables (at least 256 points per
+    // block), more when a block would otherwise need more than two passes.
     int64_t grid = cus;
-    const int64_t by_size = (n_points + kSearchThreads - 1) / kSearchThreads;
+    const int64_t by_size = (n_points + 255) / 256;
     if (by_size < grid) grid = by_size;
     const int64_t by_pass = (n_points + 2 * (int64_t)kPass - 1) / (2 * (int64_t)kPass);
     if (by_pass > grid) grid = by_pass;
@@ -503,16 +627,31 @@ static bool packed_sums(const wsm_problem *prob) {
 
 template <bool PACKED>
 static int launch_steps(const IterArgs &a, int max_iters, bool full, hipStream_t stream) {
-    const int kind = full ? WSM_KERNEL_FULL_STEP : WSM_KERNEL_SEARCH;
     for (int i = 0; i < max_iters; ++i) {
-        timing_before(kind, stream);
-        if (full)
-            step_kernel<PACKED, true><<<dim3(a.grid), dim3(kSearchThreads), 0, stream>>>(a, i);
-        else
-            step_kernel<PACKED, false><<<dim3(a.grid), dim3(kSearchThreads), 0, stream>>>(a, i);
-        timing_after(kind, stream);
+        if (full) {
+            timing_before(WSM_KERNEL_FULL_STEP, stream);
+            full_step_kernel<PACKED><<<dim3(a.grid), dim3(kSearchThreads), 0, stream>>>(a, i);
+            timing_after(WSM_KERNEL_FULL_STEP, stream);
+        } else if (a.k <= kFusedMaxK) {
+            timing_before(WSM_KERNEL_SEARCH, stream);
+            fused_step_kernel<PACKED><<<dim3(a.grid), dim3(kSearchThreads), 0, stream>>>(a, i);
+            timing_after(WSM_KERNEL_SEARCH, stream);
+        } else {
+            timing_before(WSM_KERNEL_ROWS, stream);
+            rows_kernel<PACKED><<<dim3(a.k), dim3(kSortThreads), 0, stream>>>(a, i);
+            timing_after(WSM_KERNEL_ROWS, stream);
+            timing_before(WSM_KERNEL_SEARCH, stream);
+            search_kernel<PACKED><<<dim3(a.grid), dim3(kSearchThreads), 0, stream>>>(a, i);
+            timing_after(WSM_KERNEL_SEARCH, stream);
+        }
     }
     final_kernel<PACKED><<<dim3(1), dim3(kRowThreads), 0, stream>>>(a, max_iters);
+    return hipGetLastError() == hipSuccess ? WSM_OK : WSM_EHIP;
+}
+
+// Rows of M for the state's published palette (used by the pixel map).
+int wsm_internal_palette_rows(void *state, int k, hipStream_t stream) {
+    palette_rows_kernel<<<dim3(k), dim3(kSortThreads), 0, stream>>>(make_view(state), k);
     return hipGetLastError() == hipSuccess ? WSM_OK : WSM_EHIP;
 }
 

@@ -1,17 +1,19 @@
 // Pixel mapping (Sec. 1: the second phase of color quantization) and the MSE
 // of Sec. 3.1, on gfx950.
 //
+//   rows    the neighbour matrix M of the final palette, one row per block.
 //   assign  a sort-means scan of every unique color against the final palette,
-//           starting from the color's last membership, over the truncated
-//           sorted rows each block builds in LDS (sm_block.h).  The palette
-//           index is scattered into a 2^24-entry byte table at the color's
-//           key; count * distance is summed per block for the MSE.
+//           starting from the color's last membership, over an LDS copy of M
+//           (sm_block.h).  The palette index is scattered into a 2^24-entry
+//           byte table at the color's key; count * distance is summed per
+//           block for the MSE.
 //   gather  16 pixels per lane: three 16-byte loads, 16 table lookups, one
 //           16-byte store of indices (and 48 bytes of rounded palette colors
 //           when asked for).  Block 0 also sums the MSE partials.
 #include "sm_block.h"
 
 int wsm_internal_check_problem(const wsm_problem *prob);
+int wsm_internal_palette_rows(void *state, int k, hipStream_t stream);
 
 namespace wsm {
 
@@ -22,56 +24,47 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
     StateView sv, const uint32_t *__restrict__ colors, const uint32_t *__restrict__ counts,
     int64_t n, int K, int64_t chunk, uint8_t *__restrict__ lut) {
     __shared__ float4 cen[kMaxK];
-    __shared__ RowLists L;
+    __shared__ __align__(16) uint8_t Ms[kMaxK * kRowStride];
     __shared__ double dscr[kSearchThreads / 64];
     constexpr int NT = kSearchThreads;
     const int tid = threadIdx.x;
     const int64_t start = (int64_t)blockIdx.x * chunk;
     const int64_t end = (start + chunk) < n ? (start + chunk) : n;
+    const int rs = lds_row_stride(K);
     for (int c = tid; c < K; c += NT) cen[c] = sv.pal[c];
+    load_rows<NT>(sv.rows, K, Ms);
+    __syncthreads();
     double acc = 0.0;
     uint32_t ev = 0;
     for (int64_t base = start; base < end; base += kPass) {
-        uint32_t key[kCpt];
+        uint32_t key[kCpt], cnt[kCpt];
         int pm[kCpt];
 #pragma unroll
         for (int r = 0; r < kCpt; ++r) {
             const int64_t idx = base + r * NT + tid;
             key[r] = 0u;
+            cnt[r] = 0u;
             pm[r] = 0;
             if (idx < end) {
                 key[r] = colors[idx];
+                cnt[r] = counts[idx];
                 pm[r] = sv.m[idx];
             }
         }
-        reset_row_lists(L, K);
-        __syncthreads();
 #pragma unroll
         for (int r = 0; r < kCpt; ++r) {
             if (base + r * NT >= end) break;  // block-uniform
-            const bool valid = base + r * NT + tid < end;
+            const int64_t idx = base + r * NT + tid;
+            const bool valid = idx < end;
             float x, y, z;
             unpack_key(key[r], x, y, z);
-            const float4 cp = cen[pm[r]];
-            add_threshold(L, valid, pm[r], sq_dist(x, y, z, cp.x, cp.y, cp.z));
-        }
-        __syncthreads();
-        build_row_lists<NT>(L, cen, K);
-        const bool lists_ok = !L.overflow;
-#pragma unroll
-        for (int r = 0; r < kCpt; ++r) {
-            const int64_t idx = base + r * NT + tid;
-            if (idx < end) {
-                float x, y, z;
-                unpack_key(key[r], x, y, z);
+            if (valid) {
                 float bd;
-                const int best = lists_ok ? sm_scan_lists(x, y, z, pm[r], cen, L, bd, ev)
-                                          : full_scan(x, y, z, pm[r], K, cen, bd, ev);
+                const int best = sm_scan(x, y, z, pm[r], K, cen, Ms, rs, bd, ev);
                 lut[key[r]] = (uint8_t)best;
-                acc += (double)counts[idx] * (double)bd;
+                acc += (double)cnt[r] * (double)bd;
             }
         }
-        __syncthreads();
     }
     const double s = block_sum_f64<NT>(acc, dscr);
     if (tid == 0) sv.map_part[blockIdx.x] = s;
@@ -175,6 +168,7 @@ extern "C" int wsm_map_pixels(const wsm_problem *prob, const uint8_t *rgb, int64
     int64_t chunk = (prob->n_points + nb - 1) / nb;
     chunk = (chunk + 63) / 64 * 64;
     nb = (prob->n_points + chunk - 1) / chunk;
+    if (wsm_internal_palette_rows(prob->state, prob->k, stream) != WSM_OK) return WSM_EHIP;
     timing_before(WSM_KERNEL_MAP_ASSIGN, stream);
     map_assign_kernel<<<dim3((unsigned)nb), dim3(kSearchThreads), 0, stream>>>(
         sv, prob->colors, prob->counts, prob->n_points, prob->k, chunk, lut);

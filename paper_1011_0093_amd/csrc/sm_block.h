@@ -1,21 +1,14 @@
-// Block-level building blocks of the sort-means search (Alg. 2) on gfx950,
-// shared by the iteration kernel and the pixel-map kernel.
+// Building blocks of the sort-means search (Alg. 2) on gfx950, shared by the
+// iteration kernels and the pixel-map kernel.
 //
-// Each block handles a contiguous chunk of points in passes of kPass.  For
-// the sort-means scan a point with previous center p walks row p of the
-// sorted-neighbour matrix M and stops at the first center t with
-// d(c_p,c_t)^2 >= thr(x) = 4 (1 + 2^-16) d(x,c_p)^2.  Within a pass only the
-// rows that some point of the pass starts from are ever read, and only up to
-// T_p = max thr(x) over those points: every entry past that bound stops every
-// scan of the row.  So a block builds, in LDS, exactly that part of M -- row
-// p holds the centers t != p with d(c_p,c_t)^2 < T_p, sorted by (distance,
-// index) -- and the scans over it visit the same centers, in the same order,
-// with the same break, as scans over the full sorted rows.
-//
-// Rows are built one per wave (wave w takes rows w, w + 16, ...): the wave
-// counts the row's entries with a ballot, wave 0 turns the counts into
-// offsets, and each wave then writes its rows' entries and sorts them by rank.
-// Offsets depend only on the counts, so the layout is deterministic.
+// The sorted-neighbour matrix M (Sec. 2): row p lists the centers t != p in
+// ascending (d(c_p, c_t)^2, t) order -- the row's first entry, p itself, is
+// left out, since the scan starts from the second one.  It is built once per
+// set of centers (sort_row, one block per row) and kept in device memory as
+// K rows of kRowStride bytes; a search block copies the K x (K - 1) bytes
+// into LDS.  The scan recomputes d(c_p, c_t)^2 from the centers in LDS with
+// the same expression the rows were sorted by, so the break test sees
+// bit-equal values.
 #pragma once
 
 #include "wave_ops.h"
@@ -25,21 +18,12 @@ namespace wsm {
 
 constexpr int kCpt = 4;                          // points per thread per pass
 constexpr int kPass = kSearchThreads * kCpt;     // points per pass (4096)
-constexpr int kMaxSurv = 8192;                   // truncated-row entries per pass
+constexpr int kRowStride = kMaxK;                // bytes per row of M in device memory
+constexpr int kScanBatch = 8;                    // row entries fetched per scan step
+constexpr int kFusedMaxK = 32;                   // largest K sorted inside the search block
 
-struct RowLists {
-    uint32_t thr[kMaxK];   // float bits of T_p (0: no entry can be reached)
-    uint32_t len[kMaxK];   // entries of row p
-    uint32_t off[kMaxK];   // start of row p in list[]
-    int overflow;
-    unsigned long long key[kMaxSurv];  // staging: distance bits << 32 | center
-    uint8_t list[kMaxSurv];            // the truncated sorted rows
-};
-
-__device__ __forceinline__ unsigned long long lanemask_lt() {
-    const int lane = threadIdx.x & 63;
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
+// LDS row stride for K centers: K - 1 entries rounded up to 16 bytes.
+__host__ __device__ constexpr int lds_row_stride(int K) { return ((K - 1) + 15) / 16 * 16; }
 
 // Head flag of a run of equal keys (lane 0 or a different key in the lane
 // before).
@@ -56,129 +40,116 @@ __device__ __forceinline__ bool run_tail(int key, bool valid) {
     return valid && (lane == 63 || !nv || nk != key);
 }
 
-// Record the break threshold of one point per lane into L.thr (max per
-// row).  All lanes of the wave call it.
-__device__ __forceinline__ void add_threshold(RowLists &L, bool valid, int p, float prev) {
-    const uint32_t tb = valid ? __float_as_uint(prev * kBreakScale) : 0u;
-    const int key = valid ? p : -1;
-    const uint32_t mx = wave_seg_max(run_head(key), tb);
-    if (run_tail(key, valid) && mx != 0u) atomicMax(&L.thr[p], mx);
-}
-
-// Number of entries of row p (centers t != p with d(c_p,c_t)^2 < T).  Called
-// by a whole wave; the result is the same in every lane.
-__device__ __forceinline__ uint32_t count_row(const float4 *cen, int K, int p, float T) {
-    const int lane = threadIdx.x & 63;
-    const float4 cp = cen[p];
-    uint32_t n = 0;
-    for (int c0 = 0; c0 < K; c0 += 64) {
-        const int t = c0 + lane;
-        bool s = false;
-        if (t < K && t != p) {
-            const float4 ct = cen[t];
-            s = sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z) < T;
-        }
-        n += (uint32_t)__popcll(__ballot(s));
-    }
-    return n;
-}
-
-// Write row p's n entries at `base` and sort them.  Called by a whole wave.
-__device__ __forceinline__ void fill_row(RowLists &L, const float4 *cen, int K, int p, float T,
-                                         uint32_t n, uint32_t base) {
-    const int lane = threadIdx.x & 63;
-    const float4 cp = cen[p];
-    // the entries (distance bits, center) in center order
-    uint32_t w = 0;
-    for (int c0 = 0; c0 < K; c0 += 64) {
-        const int t = c0 + lane;
-        bool s = false;
-        float d = 0.f;
-        if (t < K && t != p) {
-            const float4 ct = cen[t];
-            d = sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z);
-            s = d < T;
-        }
-        const unsigned long long m = __ballot(s);
-        if (s) {
-            const uint32_t pos = w + (uint32_t)__popcll(m & lanemask_lt());
-            L.key[base + pos] = ((unsigned long long)__float_as_uint(d) << 32) | (unsigned)t;
-        }
-        w += (uint32_t)__popcll(m);
-    }
-    // rank sort: entry j's place = number of entries with a smaller key
-    // (distance first, then index; keys are distinct)
-    for (uint32_t j0 = 0; j0 < n; j0 += 64) {
-        const uint32_t j = j0 + lane;
-        const unsigned long long kj = j < n ? L.key[base + j] : ~0ull;
-        uint32_t r = 0;
-        for (uint32_t f = 0; f < n; ++f) r += L.key[base + f] < kj;
-        if (j < n) L.list[base + r] = (uint8_t)(kj & 0xFFu);
-    }
-}
-
-// Build every row whose threshold is set.  Must be called by all threads
-// after a barrier that makes L.thr final; ends with a barrier.  Sets
-// L.overflow (and builds nothing) if the rows do not fit.
+// Sort row p of M for the K centers in LDS and write it to `row` (device
+// memory).  keys (u64) and rank (u32) are LDS scratch of kMaxK entries.  The
+// key of center t is (distance bits, t): distances are non-negative, so
+// their bit patterns order like the values, and the keys are distinct.  The
+// rank of each key is counted by NT / kMaxK threads over slices of the
+// others.  All NT threads call it; it starts with a barrier, so consecutive
+// calls may reuse the scratch.
 template <int NT>
-__device__ void build_row_lists(RowLists &L, const float4 *cen, int K) {
-    constexpr int NW = NT / 64;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    // Every lane of the wave stores the same value: no lane-0-only branch at
-    // the end of a loop whose body holds cross-lane operations.
-    for (int p = wave; p < K; p += NW) {
-        const uint32_t tb = L.thr[p];
-        const uint32_t n = tb != 0u ? count_row(cen, K, p, __uint_as_float(tb)) : 0u;
-        L.len[p] = n;
-    }
+__device__ void sort_row(const float4 *cen, int K, int p, unsigned long long *__restrict__ keys,
+                         uint32_t *rank, uint8_t *__restrict__ row) {
+    static_assert(NT % kMaxK == 0, "block size");
+    constexpr int Q = NT / kMaxK;
+    constexpr int span = kMaxK / Q;
+    const int tid = threadIdx.x;
     __syncthreads();
-    if (wave == 0) {
-        uint32_t base = 0;
-        for (int c0 = 0; c0 < K; c0 += 64) {
-            const int p = c0 + lane;
-            const uint32_t v = p < K ? L.len[p] : 0u;
-            const uint32_t incl = wave_incl_sum(v);
-            if (p < K) L.off[p] = base + incl - v;
-            base += wave_last_u32(incl);
+    const float4 cp = cen[p];
+    for (int t = tid; t < kMaxK; t += NT) {
+        unsigned long long kt = ~0ull;
+        if (t < K && t != p) {
+            const float4 ct = cen[t];
+            kt = ((unsigned long long)__float_as_uint(sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z))
+                  << 32) | (unsigned)t;
         }
-        L.overflow = base > (uint32_t)kMaxSurv ? 1 : 0;
+        keys[t] = kt;
+        rank[t] = 0u;
     }
     __syncthreads();
-    if (L.overflow) return;
-    for (int p = wave; p < K; p += NW) {
-        const uint32_t n = L.len[p];
-        if (n != 0u) fill_row(L, cen, K, p, __uint_as_float(L.thr[p]), n, L.off[p]);
+    const int t = tid % kMaxK, q = tid / kMaxK;
+    if (t < K && t != p) {
+        const unsigned long long kt = keys[t];
+        const int u0 = q * span;
+        const int u1 = (u0 + span) < K ? (u0 + span) : K;
+        // eight keys per step, read as four 16-byte words; keys past K hold
+        // the largest value and never count
+        const ulonglong2 *k2 = (const ulonglong2 *)keys;
+        uint32_t r = 0;
+        for (int u = u0; u < u1; u += 8) {
+            const ulonglong2 a = k2[u / 2], b = k2[u / 2 + 1], c = k2[u / 2 + 2], d = k2[u / 2 + 3];
+            r += (uint32_t)(a.x < kt) + (uint32_t)(a.y < kt) + (uint32_t)(b.x < kt) +
+                 (uint32_t)(b.y < kt) + (uint32_t)(c.x < kt) + (uint32_t)(c.y < kt) +
+                 (uint32_t)(d.x < kt) + (uint32_t)(d.y < kt);
+        }
+        if (Q == 1)
+            rank[t] = r;
+        else
+            atomicAdd(&rank[t], r);
     }
     __syncthreads();
+    for (int c = tid; c < K; c += NT)
+        if (c != p) row[rank[c]] = (uint8_t)c;
 }
 
-__device__ __forceinline__ void reset_row_lists(RowLists &L, int K) {
-    for (int c = threadIdx.x; c < K; c += blockDim.x) L.thr[c] = 0u;
+// Copy the K rows of M (device layout, kRowStride bytes per row) into LDS
+// rows of lds_row_stride(K) bytes.  All threads of the block call it.
+template <int NT>
+__device__ __forceinline__ void load_rows(const uint8_t *__restrict__ M, int K, uint8_t *Ms) {
+    const int rs = lds_row_stride(K);
+    const int per_row = rs / 16;
+    for (int q = threadIdx.x; q < K * per_row; q += NT) {
+        const int r = q / per_row, c = q - r * per_row;
+        *(uint4 *)(Ms + r * rs + c * 16) = *(const uint4 *)(M + (size_t)r * kRowStride + c * 16);
+    }
 }
 
-// Sort-means scan over the truncated row of p.
-__device__ __forceinline__ int sm_scan_lists(float x, float y, float z, int p,
-                                             const float4 *cen, const RowLists &L,
-                                             float &best_d, uint32_t &ev) {
+// Sort-means scan (Alg. 2, inner loop) of point x from its previous center
+// p over the LDS copy of M: starting from d(x, c_p), centers are taken in row
+// order until the first t with d(c_p, c_t)^2 >= thr = 4 (1 + 2^-16) d(x, c_p)^2.
+// Entries are fetched kScanBatch at a time (one 8-byte LDS read of the row,
+// the center reads issued together) and then taken in order; distances
+// computed past the stop are discarded.  Reads past the row's K - 1 entries
+// stay inside the LDS row (its stride is a multiple of 16) and the center
+// table.
+__device__ __forceinline__ int sm_scan(float x, float y, float z, int p, int K,
+                                       const float4 *cen, const uint8_t *Ms, int rs,
+                                       float &best_d, uint32_t &ev) {
     const float4 cp = cen[p];
     const float prev = sq_dist(x, y, z, cp.x, cp.y, cp.z);
     const float thr = prev * kBreakScale;
     float bd = prev;
     int best = p;
     ev += 1;
-    const uint32_t o = L.off[p], n = L.len[p];
-    for (uint32_t j = 0; j < n; ++j) {
-        const int t = L.list[o + j];
-        const float4 ct = cen[t];
-        const float dpt = sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z);
-        if (dpt >= thr) break;
-        const float d = sq_dist(x, y, z, ct.x, ct.y, ct.z);
-        ev += 1;
-        if (better_center(d, bd, t, best, p)) {
-            bd = d;
-            best = t;
+    const uint8_t *row = Ms + p * rs;
+    const int n = K - 1;
+    for (int j = 0; j < n; j += kScanBatch) {
+        const uint2 w8 = *(const uint2 *)(row + j);
+        float dpt[kScanBatch], d[kScanBatch];
+        int t[kScanBatch];
+#pragma unroll
+        for (int e = 0; e < kScanBatch; ++e) {
+            t[e] = ((e < 4 ? w8.x : w8.y) >> (8 * (e & 3))) & 0xFFu;
+            const float4 ct = cen[t[e]];
+            dpt[e] = sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z);
+            d[e] = sq_dist(x, y, z, ct.x, ct.y, ct.z);
         }
+        bool stop = false;
+#pragma unroll
+        for (int e = 0; e < kScanBatch; ++e) {
+            if (!stop) {
+                if (j + e >= n || dpt[e] >= thr) {
+                    stop = true;
+                } else {
+                    ev += 1;
+                    if (better_center(d[e], bd, t[e], best, p)) {
+                        bd = d[e];
+                        best = t[e];
+                    }
+                }
+            }
+        }
+        if (stop) break;
     }
     best_d = bd;
     return best;
@@ -204,8 +175,31 @@ __device__ __forceinline__ int full_scan(float x, float y, float z, int p, int K
     return best;
 }
 
-// Block sums in a fixed order: waves reduce with DPP, wave totals are added
-// in wave order.  Result valid in thread 0.
+// Block sums of a double and a u64 in a fixed order: waves reduce with DPP,
+// wave totals are added in wave order.  Results valid in thread 0.
+template <int NT>
+__device__ __forceinline__ void block_sum2(double &v, unsigned long long &e, double *dscr,
+                                           unsigned long long *uscr) {
+    v = wave_sum_f64(v);
+    e = wave_sum_u64(e);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 63) {
+        dscr[wave] = v;
+        uscr[wave] = e;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        unsigned long long u = 0;
+        for (int w = 0; w < NT / 64; ++w) {
+            s += dscr[w];
+            u += uscr[w];
+        }
+        v = s;
+        e = u;
+    }
+}
+
 template <int NT>
 __device__ __forceinline__ double block_sum_f64(double v, double *scr) {
     v = wave_sum_f64(v);
@@ -213,19 +207,6 @@ __device__ __forceinline__ double block_sum_f64(double v, double *scr) {
     if (lane == 63) scr[wave] = v;
     __syncthreads();
     double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < NT / 64; ++w) s += scr[w];
-    return s;
-}
-
-template <int NT>
-__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v,
-                                                            unsigned long long *scr) {
-    v = wave_sum_u64(v);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 63) scr[wave] = v;
-    __syncthreads();
-    unsigned long long s = 0;
     if (threadIdx.x == 0)
         for (int w = 0; w < NT / 64; ++w) s += scr[w];
     return s;

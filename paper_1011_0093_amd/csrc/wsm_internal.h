@@ -15,7 +15,8 @@ constexpr int kMaxK = WSM_MAX_K;
 constexpr int kHistory = WSM_HISTORY;
 constexpr int kMaxGrid = 2048;          // upper bound on search-kernel blocks
 constexpr int kSearchThreads = 1024;    // threads per search block (16 waves)
-constexpr int kRowThreads = 256;        // threads per rows block (one per center)
+constexpr int kRowThreads = 256;        // threads of the single-block final update
+constexpr int kSortThreads = 1024;      // threads per rows block (one row of M each)
 constexpr uint32_t kMagic = 0x574D5331u;
 
 constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -63,7 +64,8 @@ constexpr size_t kOffEvalPart = kOffSsePart + 2 * kMaxGrid * 8;       // u64[2][
 constexpr size_t kOffSseHist = kOffEvalPart + 2 * kMaxGrid * 8;       // double[kHistory]
 constexpr size_t kOffEvalHist = kOffSseHist + kHistory * 8;           // int64[kHistory]
 constexpr size_t kOffMapPart = kOffEvalHist + kHistory * 8;           // double[kMaxGrid]
-constexpr size_t kOffMembership = align_up(kOffMapPart + kMaxGrid * 8, 256);
+constexpr size_t kOffRows = align_up(kOffMapPart + kMaxGrid * 8, 256);  // u8[256][256]
+constexpr size_t kOffMembership = kOffRows + (size_t)kMaxK * kMaxK;
 
 inline size_t state_bytes_for(int64_t n_points) {
     return kOffMembership + align_up((size_t)n_points, 256);
@@ -79,6 +81,7 @@ struct StateView {
     double *sse_hist;
     long long *eval_hist;
     double *map_part;     // [kMaxGrid]
+    uint8_t *rows;        // [256][256]: sorted neighbour rows (M without self)
     uint8_t *m;           // [n_points]
 };
 
@@ -93,6 +96,7 @@ inline StateView make_view(void *state) {
     v.sse_hist = (double *)(b + kOffSseHist);
     v.eval_hist = (long long *)(b + kOffEvalHist);
     v.map_part = (double *)(b + kOffMapPart);
+    v.rows = (uint8_t *)(b + kOffRows);
     v.m = (uint8_t *)(b + kOffMembership);
     return v;
 }
