@@ -84,6 +84,9 @@ def main():
     lut = torch.empty(1 << 24, dtype=torch.uint8, device=dev)
     idx_host = torch.empty(sum(Ks), dtype=torch.int32).pin_memory()
     idx_dev = torch.empty(sum(Ks), dtype=torch.int32, device=dev)
+    # one state buffer per K, re-initialised every step (persistent buffers,
+    # as a serving loop would keep them)
+    states = {}
 
     def step(record=None):
         wsm.reduce_colors_into(img, colors, counts, nu, ws)
@@ -100,7 +103,8 @@ def main():
         for K in Ks:
             pal = wsm.palette_from_indices(col, idx_dev[off:off + K])
             off += K
-            st = wsm.init(col, cnt, N, pal)
+            st = wsm.init(col, cnt, N, pal, reuse=states.get(K))
+            states[K] = st
             st.iterate(MAX_ITERS, EPS)
             index, _, mse = wsm.map_pixels(st, img, lut=lut)
             out[K] = (st, mse, pal)
@@ -154,8 +158,11 @@ def main():
         st, mse, pal = out[K]
         iters = st.info()["iters"]
 
+        scratch = {}
+
         def run_sm(pal=pal):
-            s = wsm.init(col, cnt, N, pal)
+            s = wsm.init(col, cnt, N, pal, reuse=scratch.get("sm"))
+            scratch["sm"] = s
             s.iterate(MAX_ITERS, EPS)
             return s
 
@@ -167,12 +174,12 @@ def main():
         holder = {}
 
         def run_full(pal=pal):
-            s = wsm.init(col, cnt, N, pal)
+            s = wsm.init(col, cnt, N, pal, reuse=holder.get("full"))
             s.iterate_full(MAX_ITERS, EPS)
             holder["full"] = s
 
         def run_pix(pal=pal):
-            s = wsm.init_pixels(img, pal)
+            s = wsm.init_pixels(img, pal, reuse=holder.get("pix"))
             s.iterate_full(MAX_ITERS, EPS)
             holder["pix"] = s
 

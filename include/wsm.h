@@ -10,9 +10,11 @@
  * Conventions for every function below:
  *   - Pointers are DEVICE pointers unless the comment says "host".
  *   - All device work is enqueued asynchronously on `stream`; no function
- *     allocates device memory, frees it, or synchronizes the host.  Every
- *     buffer is owned by the caller and must stay valid until the enqueued
- *     work has finished.
+ *     allocates device memory, frees it, or synchronizes the host (the one
+ *     exception is the HIP graph the runtime builds when an iterate call
+ *     repeats earlier arguments; see wsm_set_graph_replay).  Every buffer is owned
+ *     by the caller and must stay valid until the enqueued work has
+ *     finished.
  *   - Return value: WSM_OK (0) or a negative wsm_status.  Arguments are fully
  *     validated on the host before anything is enqueued; on error nothing is
  *     enqueued and no output is written.  WSM_EHIP reports a failed launch.
@@ -167,6 +169,22 @@ int wsm_state_views(const wsm_problem *prob, wsm_views *views /* host */);
 int wsm_map_pixels(const wsm_problem *prob, const uint8_t *rgb,
                    int64_t n_pixels, uint8_t *lut, uint8_t *index_out,
                    uint8_t *rgb_out, double *mse_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Launch replay (not part of the method).  wsm_iterate and
+ * wsm_iterate_full enqueue a fixed sequence of kernel launches that depends
+ * only on their arguments.  By default the library remembers each set of
+ * arguments (state, points, K, grid, eps, max_iters); the second call with
+ * the same set records the sequence into a HIP graph, on a stream of its
+ * own, and that call and every later one replay the graph on `stream`,
+ * which shortens the gaps between the launches.  The recording call lets the
+ * HIP runtime create the graph (host work of a few milliseconds; the runtime
+ * may reserve device memory for it).  Up to 64 argument sets are kept until
+ * the process ends; further sets, calls on a stream that is being captured,
+ * and calls while a timing hook is attached launch directly.  wsm_set_graph_replay(0) makes every call launch
+ * directly, (1) restores replay; it returns the previous setting.  Results
+ * are the same either way. */
+int wsm_set_graph_replay(int enable);
 
 /* ------------------------------------------------------------------ */
 /* Measurement support (not part of the method).  While attached, every

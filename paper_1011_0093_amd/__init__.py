@@ -91,10 +91,11 @@ def _load():
     lib.wsm_timing_attach.argtypes = [I32, I32]
     lib.wsm_timing_read.argtypes = [ctypes.POINTER(ctypes.c_float), I32, ctypes.POINTER(I32)]
     lib.wsm_timing_detach.argtypes = []
+    lib.wsm_set_graph_replay.argtypes = [I32]
     for f in ("wsm_reduce_workspace_bytes", "wsm_reduce_colors", "wsm_state_bytes", "wsm_init",
               "wsm_init_pixels", "wsm_iterate", "wsm_iterate_full", "wsm_state_views",
               "wsm_map_pixels", "wsm_gather_palette", "wsm_timing_attach", "wsm_timing_read",
-              "wsm_timing_detach"):
+              "wsm_timing_detach", "wsm_set_graph_replay"):
         getattr(lib, f).restype = I32
     return lib
 
@@ -247,28 +248,37 @@ def _new_state(n_points: int, k: int, device) -> torch.Tensor:
     return buf[off:off + nbytes]
 
 
-def init(colors: torch.Tensor, counts: torch.Tensor, n_pixels: int, palette: torch.Tensor) -> State:
+def init(colors: torch.Tensor, counts: torch.Tensor, n_pixels: int, palette: torch.Tensor,
+         reuse: "State | None" = None) -> State:
     """Bind a state to a unique-color table and an initial palette
-    (float32 [k, 3] on the GPU)."""
+    (float32 [k, 3] on the GPU).  With `reuse`, that state's device buffer is
+    re-initialised instead of allocating a new one (it must be large enough)."""
     colors = _dev(colors, torch.int32, "colors")
     counts = _dev(counts, torch.int32, "counts")
     palette = _dev(palette, torch.float32, "palette")
     k = palette.shape[0]
     n = colors.numel()
-    buf = _new_state(n, k, colors.device)
+    if reuse is not None and reuse.buf.numel() >= state_bytes(n, k) and reuse.buf.device == colors.device:
+        buf = reuse.buf
+    else:
+        buf = _new_state(n, k, colors.device)
     prob = _Problem()
     _check(_lib.wsm_init(ctypes.byref(prob), _ptr(buf), buf.numel(), _ptr(colors), _ptr(counts),
                          n, int(n_pixels), k, _ptr(palette), _stream()), "wsm_init")
     return State(prob, buf, (colors, counts, palette))
 
 
-def init_pixels(img: torch.Tensor, palette: torch.Tensor) -> State:
-    """Bind a state to every pixel of an image (weight 1 each): Alg. 1."""
+def init_pixels(img: torch.Tensor, palette: torch.Tensor, reuse: "State | None" = None) -> State:
+    """Bind a state to every pixel of an image (weight 1 each): Alg. 1.
+    `reuse` as for init()."""
     img = _dev(img, torch.uint8, "img")
     palette = _dev(palette, torch.float32, "palette")
     k = palette.shape[0]
     n = img.numel() // 3
-    buf = _new_state(n, k, img.device)
+    if reuse is not None and reuse.buf.numel() >= state_bytes(n, k) and reuse.buf.device == img.device:
+        buf = reuse.buf
+    else:
+        buf = _new_state(n, k, img.device)
     prob = _Problem()
     _check(_lib.wsm_init_pixels(ctypes.byref(prob), _ptr(buf), buf.numel(), _ptr(img), n, k,
                                 _ptr(palette), _stream()), "wsm_init_pixels")
@@ -316,6 +326,12 @@ def palette_from_indices(colors: torch.Tensor, indices, out: torch.Tensor | None
 
 KERNELS = dict(reduce_partition=1, reduce_compact=2, rows=3, search=4, map_assign=5,
                map_gather=6, full_step=7)
+
+
+def set_graph_replay(enable: bool) -> bool:
+    """Turn the replay of iteration launch sequences from HIP graphs on or
+    off; returns the previous setting."""
+    return bool(_lib.wsm_set_graph_replay(1 if enable else 0))
 
 
 class kernel_timer:

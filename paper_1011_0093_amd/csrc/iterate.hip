@@ -26,6 +26,10 @@
 // triple-buffered, so no launch reads what another block of the same launch
 // writes.  A single-block kernel applies the final update after the last
 // step and copies the result to the public slot 0.
+#include <cstring>
+#include <mutex>
+#include <vector>
+
 #include "sm_block.h"
 
 namespace wsm {
@@ -95,14 +99,27 @@ __device__ Record update_phase(const IterArgs &a, int i, float4 *cen, bool write
             cv[r].z = update ? upd.z : old.z;
         }
     }
+    // Lane l of the first wave sums partials l, l + 64, l + 128, ... in that
+    // order; the loads of eight of them are issued together.
     double s = 0.0;
     unsigned long long e = 0;
     if (tid < 64) {
         const double *sp = a.sv.sse_part + (size_t)((i + 1) & 1) * kMaxGrid;
         const unsigned long long *ep = a.sv.eval_part + (size_t)((i + 1) & 1) * kMaxGrid;
-        for (int g = tid; g < a.grid; g += 64) {
-            s += sp[g];
-            e += ep[g];
+        for (int g0 = 0; g0 < a.grid; g0 += 64 * 8) {
+            double v[8];
+            unsigned long long w[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int g = g0 + u * 64 + tid;
+                v[u] = g < a.grid ? sp[g] : 0.0;
+                w[u] = g < a.grid ? ep[g] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                s += v[u];
+                e += w[u];
+            }
         }
     }
 #pragma unroll
@@ -655,14 +672,124 @@ int wsm_internal_palette_rows(void *state, int k, hipStream_t stream) {
     return hipGetLastError() == hipSuccess ? WSM_OK : WSM_EHIP;
 }
 
+static int launch_direct(const IterArgs &a, int max_iters, bool full, bool packed,
+                         hipStream_t stream) {
+    return packed ? launch_steps<true>(a, max_iters, full, stream)
+                  : launch_steps<false>(a, max_iters, full, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Replay of a call's launch sequence from a HIP graph.  A sequence depends
+// only on the call's arguments.  The first call with a set of arguments
+// launches directly and remembers them; the second records the sequence
+// (on a stream of the library's own) and every later one replays it on the
+// caller's stream, so one-off calls never pay for the recording.  Graphs
+// are kept until the process ends; past kMaxGraphs distinct argument sets,
+// calls launch directly.
+namespace {
+
+struct GraphEntry {
+    int device;
+    const void *state;
+    const uint32_t *colors, *counts;
+    const uint8_t *rgb;
+    int64_t n, n_pixels;
+    int is_pixels, k, grid, max_iters, full, packed;
+    uint64_t eps_bits;
+    hipGraphExec_t exec;
+};
+
+constexpr size_t kMaxGraphs = 64;
+constexpr int kMaxDevices = 64;
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;
+hipStream_t g_capture_stream[kMaxDevices] = {};
+int g_graph_replay = 1;
+
+bool same_call(const GraphEntry &e, const GraphEntry &q) {
+    return e.device == q.device && e.state == q.state && e.colors == q.colors &&
+           e.counts == q.counts && e.rgb == q.rgb && e.n == q.n && e.n_pixels == q.n_pixels &&
+           e.is_pixels == q.is_pixels && e.k == q.k && e.grid == q.grid &&
+           e.max_iters == q.max_iters && e.full == q.full && e.packed == q.packed &&
+           e.eps_bits == q.eps_bits;
+}
+
+}  // namespace
+
+static int launch_replayed(const IterArgs &a, int max_iters, bool full, bool packed,
+                           hipStream_t stream) {
+    GraphEntry q{};
+    if (hipGetDevice(&q.device) != hipSuccess || q.device < 0 || q.device >= kMaxDevices)
+        return launch_direct(a, max_iters, full, packed, stream);
+    q.state = a.sv.hdr;
+    q.colors = a.pts.colors;
+    q.counts = a.pts.counts;
+    q.rgb = a.pts.rgb;
+    q.n = a.pts.n;
+    q.n_pixels = a.n_pixels;
+    q.is_pixels = a.pts.is_pixels;
+    q.k = a.k;
+    q.grid = a.grid;
+    q.max_iters = max_iters;
+    q.full = full ? 1 : 0;
+    q.packed = packed ? 1 : 0;
+    std::memcpy(&q.eps_bits, &a.eps, sizeof(q.eps_bits));
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    GraphEntry *hit = nullptr;
+    for (GraphEntry &e : g_graphs)
+        if (same_call(e, q)) hit = &e;
+    if (!hit) {
+        // first sighting: remember the arguments, launch directly
+        if (g_graphs.size() < kMaxGraphs) {
+            q.exec = nullptr;
+            g_graphs.push_back(q);
+        }
+        return launch_direct(a, max_iters, full, packed, stream);
+    }
+    hipGraphExec_t exec = hit->exec;
+    if (!exec) {
+        hipStream_t &cs = g_capture_stream[q.device];
+        if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+            cs = nullptr;
+            return WSM_EHIP;
+        }
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return WSM_EHIP;
+        const int rc = launch_direct(a, max_iters, full, packed, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t end = hipStreamEndCapture(cs, &graph);
+        if (rc != WSM_OK || end != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            return WSM_EHIP;
+        }
+        const hipError_t inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (inst != hipSuccess) return WSM_EHIP;
+        hit->exec = exec;
+    }
+    return hipGraphLaunch(exec, stream) == hipSuccess ? WSM_OK : WSM_EHIP;
+}
+
 static int iterate_impl(const wsm_problem *prob, int max_iters, double eps, bool full,
                         hipStream_t stream) {
     int rc = check_iter_args(prob, max_iters, eps);
     if (rc != WSM_OK) return rc;
     const IterArgs a = make_args(prob, eps);
+    const bool packed = packed_sums(prob);
     (void)hipGetLastError();
-    return packed_sums(prob) ? launch_steps<true>(a, max_iters, full, stream)
-                             : launch_steps<false>(a, max_iters, full, stream);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return WSM_EHIP;
+    if (g_graph_replay && cap == hipStreamCaptureStatusNone && !timing_attached())
+        return launch_replayed(a, max_iters, full, packed, stream);
+    return launch_direct(a, max_iters, full, packed, stream);
+}
+
+extern "C" int wsm_set_graph_replay(int enable) {
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    const int prev = g_graph_replay;
+    g_graph_replay = enable ? 1 : 0;
+    return prev;
 }
 
 extern "C" int wsm_iterate(const wsm_problem *prob, int max_iters, double eps,

@@ -94,13 +94,30 @@ __device__ void sort_row(const float4 *cen, int K, int p, unsigned long long *__
 
 // Copy the K rows of M (device layout, kRowStride bytes per row) into LDS
 // rows of lds_row_stride(K) bytes.  All threads of the block call it.
+// All of a thread's loads are issued before the first LDS store.
 template <int NT>
 __device__ __forceinline__ void load_rows(const uint8_t *__restrict__ M, int K, uint8_t *Ms) {
+    constexpr int kRegs = (kMaxK * kRowStride / 16 + NT - 1) / NT;
     const int rs = lds_row_stride(K);
     const int per_row = rs / 16;
-    for (int q = threadIdx.x; q < K * per_row; q += NT) {
-        const int r = q / per_row, c = q - r * per_row;
-        *(uint4 *)(Ms + r * rs + c * 16) = *(const uint4 *)(M + (size_t)r * kRowStride + c * 16);
+    const int nq = K * per_row;
+    uint4 v[kRegs];
+#pragma unroll
+    for (int u = 0; u < kRegs; ++u) {
+        const int q = threadIdx.x + u * NT;
+        v[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (q < nq) {
+            const int r = q / per_row, c = q - r * per_row;
+            v[u] = *(const uint4 *)(M + (size_t)r * kRowStride + c * 16);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kRegs; ++u) {
+        const int q = threadIdx.x + u * NT;
+        if (q < nq) {
+            const int r = q / per_row, c = q - r * per_row;
+            *(uint4 *)(Ms + r * rs + c * 16) = v[u];
+        }
     }
 }
 

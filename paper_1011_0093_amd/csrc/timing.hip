@@ -21,6 +21,8 @@ TimingState g_timing;
 
 namespace wsm {
 
+bool timing_attached() { return g_timing.which != 0; }
+
 void timing_before(int kind, hipStream_t stream) {
     if (g_timing.which != kind || g_timing.count >= g_timing.capacity) return;
     (void)hipEventRecord(g_timing.begin[g_timing.count], stream);

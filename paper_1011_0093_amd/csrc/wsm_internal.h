@@ -23,6 +23,7 @@ constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Measurement hook (timing.hip): no-ops unless a caller attached events to
 // this kernel kind.
+bool timing_attached();
 void timing_before(int kind, hipStream_t stream);
 void timing_after(int kind, hipStream_t stream);
 

@@ -413,3 +413,52 @@ def test_large_lockstep_and_map_sample():
     check_assignment(sub.astype(np.float64), c, idx.cpu().numpy()[sel], ref_idx)
     ci, cmse = oracle.assign_colors(colors, _u32(cnt), img.shape[0] * img.shape[1], m, c)
     assert float(mse.item()) == pytest.approx(cmse, rel=MSE_RTOL)
+
+
+# ---------------------------------------------------------------------------
+# Launch replay from HIP graphs: bit-identical to direct launches.
+
+@pytest.mark.parametrize("K", [32, 256])
+def test_graph_replay_matches_direct_launches(K):
+    """The recorded launch sequence of an iterate call, replayed several
+    times with other eager work and host synchronisations in between, gives
+    exactly the palette, memberships and histories of direct launches
+    (K = 32 runs the single-launch step, K = 256 the rows + search pair).
+    The first call with a set of arguments launches directly, the second
+    records, later ones replay."""
+    wsm = _wsm()
+    _say("graph replay medium seed 0 K", K, "12 iterations, 4 replays")
+    img = synth.workload_image("medium", 0)
+    g = _gpu_img(img)
+    col, cnt = wsm.reduce_colors(g)
+    n_pix = img.shape[0] * img.shape[1]
+    pal = wsm.palette_from_indices(col, synth.init_indices(1, col.numel(), K))
+    prev = wsm.set_graph_replay(False)
+    try:
+        ref = wsm.init(col, cnt, n_pix, pal)
+        ref.iterate(12, 0.0)
+        ref_pal = ref.palette().cpu()
+        ref_m = ref.membership().cpu()
+        ref_sse, ref_ev = ref.history()
+        wsm.set_graph_replay(True)
+        st = None
+        for rep in range(4):
+            st = wsm.init(col, cnt, n_pix, pal, reuse=st)
+            st.iterate(12, 0.0)
+            wsm.map_pixels(st, g)          # other work on the stream between replays
+            torch.cuda.synchronize()
+            sse, ev = st.history()
+            assert torch.equal(st.palette().cpu(), ref_pal), rep
+            assert torch.equal(st.membership().cpu(), ref_m), rep
+            assert np.array_equal(sse, ref_sse) and np.array_equal(ev, ref_ev), rep
+            assert st.info() == ref.info(), rep
+        # resumed calls (two more argument sets): the first pair launches
+        # directly, the second records and replays
+        for rep in range(3):
+            st = wsm.init(col, cnt, n_pix, pal, reuse=st)
+            st.iterate(5, 0.0)
+            st.iterate(7, 0.0)
+            torch.cuda.synchronize()
+            assert torch.equal(st.palette().cpu(), ref_pal), rep
+    finally:
+        wsm.set_graph_replay(prev)
