@@ -35,6 +35,25 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM traffic of one search_kernel launch on this workload: two rocprofv3
+# counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by
+# what the counter reads for a 256 MiB reference copy in the same program
+# (profiles/search_kernel_512x512_traffic.md).  It describes the kernel
+# sources it was measured on (hash below); for any other sources the bench
+# reports null.
+SEARCH_TRAFFIC_BYTES = 3064495
+SEARCH_TRAFFIC_SRC = "21ad572e052939b3"
+_KERNEL_SOURCES = ("iterate.hip", "sm_block.h", "wave_ops.h", "wsm_internal.h")
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in _KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1011_0093_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 FP32_PEAK_TFLOPS = 157.3
 EPS = 1e-4
 MAX_ITERS = 50
@@ -51,6 +70,9 @@ def parse():
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB before the steps "
+                         "(a reference dispatch for hardware traffic counters)")
     return ap.parse_args()
 
 
@@ -109,6 +131,14 @@ def main():
             index, _, mse = wsm.map_pixels(st, img, lut=lut)
             out[K] = (st, mse, pal)
         return n_unique, out
+
+    if args.copy_mb > 0:
+        src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()
@@ -216,10 +246,13 @@ def main():
     dur_ms = float(np.mean(launches))
     bytes_per_launch = 10.0 * n_unique
     achieved = bytes_per_launch / (dur_ms * 1e-3) / 1e9
+    traffic = None
+    if SEARCH_TRAFFIC_BYTES is not None and kernel_sources_hash() == SEARCH_TRAFFIC_SRC:
+        traffic = SEARCH_TRAFFIC_BYTES
     roofline = dict(kernel="wsm::search_kernel<true>", bound="hbm", achieved=achieved,
-                    peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=None,
-                    avg_launch_us=dur_ms * 1e3, launches=len(launches),
-                    bytes_per_launch=bytes_per_launch)
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                    traffic_unit="bytes per launch", avg_launch_us=dur_ms * 1e3,
+                    launches=len(launches), bytes_per_launch=bytes_per_launch)
 
     large = None
     if not args.no_large:

@@ -188,9 +188,11 @@ int wsm_set_graph_replay(int enable);
 
 /* ------------------------------------------------------------------ */
 /* Measurement support (not part of the method).  While attached, every
- * launch of the kernel `which` made by this process is bracketed by two HIP
- * events recorded on the stream it is launched on; wsm_timing_read waits for
- * them and returns the first min(count, capacity) durations in ms.  The hook
+ * launch of the kernel `which` made by this process is made with
+ * hipExtLaunchKernelGGL and two HIP events, which the runtime records when
+ * the kernel starts and when it ends, on the stream it is launched on;
+ * wsm_timing_read waits for them and returns the first min(count, capacity)
+ * durations in ms.  The hook
  * is process-wide and not thread-safe; attach creates 2 * capacity events
  * and detach destroys them.  Attaching while attached returns WSM_EINVAL. */
 typedef enum {

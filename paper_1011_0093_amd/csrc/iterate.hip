@@ -646,20 +646,16 @@ template <bool PACKED>
 static int launch_steps(const IterArgs &a, int max_iters, bool full, hipStream_t stream) {
     for (int i = 0; i < max_iters; ++i) {
         if (full) {
-            timing_before(WSM_KERNEL_FULL_STEP, stream);
-            full_step_kernel<PACKED><<<dim3(a.grid), dim3(kSearchThreads), 0, stream>>>(a, i);
-            timing_after(WSM_KERNEL_FULL_STEP, stream);
+            WSM_LAUNCH(WSM_KERNEL_FULL_STEP, full_step_kernel<PACKED>, dim3(a.grid),
+                       dim3(kSearchThreads), stream, a, i);
         } else if (a.k <= kFusedMaxK) {
-            timing_before(WSM_KERNEL_SEARCH, stream);
-            fused_step_kernel<PACKED><<<dim3(a.grid), dim3(kSearchThreads), 0, stream>>>(a, i);
-            timing_after(WSM_KERNEL_SEARCH, stream);
+            WSM_LAUNCH(WSM_KERNEL_SEARCH, fused_step_kernel<PACKED>, dim3(a.grid),
+                       dim3(kSearchThreads), stream, a, i);
         } else {
-            timing_before(WSM_KERNEL_ROWS, stream);
-            rows_kernel<PACKED><<<dim3(a.k), dim3(kSortThreads), 0, stream>>>(a, i);
-            timing_after(WSM_KERNEL_ROWS, stream);
-            timing_before(WSM_KERNEL_SEARCH, stream);
-            search_kernel<PACKED><<<dim3(a.grid), dim3(kSearchThreads), 0, stream>>>(a, i);
-            timing_after(WSM_KERNEL_SEARCH, stream);
+            WSM_LAUNCH(WSM_KERNEL_ROWS, rows_kernel<PACKED>, dim3(a.k), dim3(kSortThreads), stream,
+                       a, i);
+            WSM_LAUNCH(WSM_KERNEL_SEARCH, search_kernel<PACKED>, dim3(a.grid),
+                       dim3(kSearchThreads), stream, a, i);
         }
     }
     final_kernel<PACKED><<<dim3(1), dim3(kRowThreads), 0, stream>>>(a, max_iters);

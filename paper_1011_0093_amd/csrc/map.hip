@@ -169,23 +169,23 @@ extern "C" int wsm_map_pixels(const wsm_problem *prob, const uint8_t *rgb, int64
     chunk = (chunk + 63) / 64 * 64;
     nb = (prob->n_points + chunk - 1) / chunk;
     if (wsm_internal_palette_rows(prob->state, prob->k, stream) != WSM_OK) return WSM_EHIP;
-    timing_before(WSM_KERNEL_MAP_ASSIGN, stream);
-    map_assign_kernel<<<dim3((unsigned)nb), dim3(kSearchThreads), 0, stream>>>(
-        sv, prob->colors, prob->counts, prob->n_points, prob->k, chunk, lut);
-    timing_after(WSM_KERNEL_MAP_ASSIGN, stream);
+    WSM_LAUNCH(WSM_KERNEL_MAP_ASSIGN, map_assign_kernel, dim3((unsigned)nb), dim3(kSearchThreads),
+               stream, sv, prob->colors, prob->counts, prob->n_points, prob->k, chunk, lut);
     if (hipGetLastError() != hipSuccess) return WSM_EHIP;
     const int64_t per_block = (int64_t)kMapThreads * kGatherPpt;
     const int64_t gb = (n_pixels + per_block - 1) / per_block;
     const bool vec = (((uintptr_t)rgb & 15u) == 0u) && (((uintptr_t)index_out & 15u) == 0u) &&
                      (!rgb_out || (((uintptr_t)rgb_out & 15u) == 0u));
-    timing_before(WSM_KERNEL_MAP_GATHER, stream);
     if (vec)
-        map_gather_kernel<true><<<dim3((unsigned)gb), dim3(kMapThreads), 0, stream>>>(
-            rgb, n_pixels, lut, index_out, rgb_out, mse_out, sv.map_part, (int)nb, sv.pal, prob->k);
+        WSM_LAUNCH(WSM_KERNEL_MAP_GATHER, map_gather_kernel<true>, dim3((unsigned)gb),
+                   dim3(kMapThreads), stream, rgb, n_pixels, (const uint8_t *)lut, index_out,
+                   rgb_out, mse_out, (const double *)sv.map_part, (int)nb, (const float4 *)sv.pal,
+                   prob->k);
     else
-        map_gather_kernel<false><<<dim3((unsigned)gb), dim3(kMapThreads), 0, stream>>>(
-            rgb, n_pixels, lut, index_out, rgb_out, mse_out, sv.map_part, (int)nb, sv.pal, prob->k);
-    timing_after(WSM_KERNEL_MAP_GATHER, stream);
+        WSM_LAUNCH(WSM_KERNEL_MAP_GATHER, map_gather_kernel<false>, dim3((unsigned)gb),
+                   dim3(kMapThreads), stream, rgb, n_pixels, (const uint8_t *)lut, index_out,
+                   rgb_out, mse_out, (const double *)sv.map_part, (int)nb, (const float4 *)sv.pal,
+                   prob->k);
     if (hipGetLastError() != hipSuccess) return WSM_EHIP;
     return WSM_OK;
 }

@@ -333,19 +333,18 @@ extern "C" int wsm_reduce_colors(const uint8_t *rgb, int64_t n_pixels, uint32_t 
     int32_t *err = (int32_t *)(ws + L.off_status + kSlices * 8);
     const bool vec = (L.ppt == kMaxPpt) && (((uintptr_t)rgb & 15u) == 0u);
     (void)hipGetLastError();
-    timing_before(WSM_KERNEL_REDUCE_PARTITION, stream);
     if (vec)
-        reduce_partition_kernel<true><<<dim3((unsigned)L.ntiles), dim3(kPartThreads), 0, stream>>>(
-            rgb, n_pixels, L.ppt, L.tile, L.ntiles, keys16, info, status, err);
+        WSM_LAUNCH(WSM_KERNEL_REDUCE_PARTITION, reduce_partition_kernel<true>,
+                   dim3((unsigned)L.ntiles), dim3(kPartThreads), stream, rgb, n_pixels, L.ppt,
+                   L.tile, L.ntiles, keys16, info, status, err);
     else
-        reduce_partition_kernel<false><<<dim3((unsigned)L.ntiles), dim3(kPartThreads), 0, stream>>>(
-            rgb, n_pixels, L.ppt, L.tile, L.ntiles, keys16, info, status, err);
-    timing_after(WSM_KERNEL_REDUCE_PARTITION, stream);
+        WSM_LAUNCH(WSM_KERNEL_REDUCE_PARTITION, reduce_partition_kernel<false>,
+                   dim3((unsigned)L.ntiles), dim3(kPartThreads), stream, rgb, n_pixels, L.ppt,
+                   L.tile, L.ntiles, keys16, info, status, err);
     if (hipGetLastError() != hipSuccess) return WSM_EHIP;
-    timing_before(WSM_KERNEL_REDUCE_COMPACT, stream);
-    reduce_compact_kernel<<<dim3(kSlices), dim3(kCompactThreads), 0, stream>>>(
-        keys16, info, L.ntiles, L.tile, colors, counts, status, n_unique, err);
-    timing_after(WSM_KERNEL_REDUCE_COMPACT, stream);
+    WSM_LAUNCH(WSM_KERNEL_REDUCE_COMPACT, reduce_compact_kernel, dim3(kSlices),
+               dim3(kCompactThreads), stream, (const uint16_t *)keys16, (const uint32_t *)info,
+               L.ntiles, L.tile, colors, counts, status, n_unique, err);
     if (hipGetLastError() != hipSuccess) return WSM_EHIP;
     return WSM_OK;
 }

@@ -1,7 +1,8 @@
 // Measurement hook of the C ABI: while attached, every launch of one chosen
-// kernel is bracketed by a pair of HIP events recorded on the stream the
-// kernel is launched on, so a caller can time that kernel's launches inside
-// a larger sequence without a profiler.  Not used on the normal path.
+// kernel is made with hipExtLaunchKernelGGL and a pair of HIP events that
+// the runtime records when the kernel starts and ends, on the stream it is
+// launched on, so a caller can time that kernel's launches inside a larger
+// sequence without a profiler.  Not used on the normal path.
 #include <vector>
 
 #include "wsm_internal.h"
@@ -23,15 +24,12 @@ namespace wsm {
 
 bool timing_attached() { return g_timing.which != 0; }
 
-void timing_before(int kind, hipStream_t stream) {
-    if (g_timing.which != kind || g_timing.count >= g_timing.capacity) return;
-    (void)hipEventRecord(g_timing.begin[g_timing.count], stream);
-}
-
-void timing_after(int kind, hipStream_t stream) {
-    if (g_timing.which != kind || g_timing.count >= g_timing.capacity) return;
-    (void)hipEventRecord(g_timing.end[g_timing.count], stream);
+bool timing_claim(int kind, hipEvent_t *begin, hipEvent_t *end) {
+    if (g_timing.which != kind || g_timing.count >= g_timing.capacity) return false;
+    *begin = g_timing.begin[g_timing.count];
+    *end = g_timing.end[g_timing.count];
     ++g_timing.count;
+    return true;
 }
 
 }  // namespace wsm

@@ -3,6 +3,7 @@
 // uses.  Nothing here is part of the C ABI (see include/wsm.h).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -21,11 +22,22 @@ constexpr uint32_t kMagic = 0x574D5331u;
 
 constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Measurement hook (timing.hip): no-ops unless a caller attached events to
-// this kernel kind.
+// Measurement hook (timing.hip).  timing_claim hands out the next pair of
+// events when a caller attached events to this kernel kind; WSM_LAUNCH then
+// launches through hipExtLaunchKernelGGL, which records them at the
+// kernel's start and end.
 bool timing_attached();
-void timing_before(int kind, hipStream_t stream);
-void timing_after(int kind, hipStream_t stream);
+bool timing_claim(int kind, hipEvent_t *begin, hipEvent_t *end);
+
+#define WSM_LAUNCH(KIND, KERNEL, GRID, BLOCK, STREAM, ...)                                   \
+    do {                                                                                     \
+        hipEvent_t wsm_tb_, wsm_te_;                                                         \
+        if (::wsm::timing_claim((KIND), &wsm_tb_, &wsm_te_))                                 \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, wsm_tb_, wsm_te_, 0,       \
+                                  __VA_ARGS__);                                              \
+        else                                                                                 \
+            KERNEL<<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);                                 \
+    } while (0)
 
 // ---------------------------------------------------------------------------
 // Per-iteration record.  Two copies live in the state header: the kernels of
