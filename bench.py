@@ -228,14 +228,14 @@ def main():
             equal_palette_full=same_full, equal_palette_pixels=same_pix,
             mse_wsm=float(out[K][1].item()), mse_full=float(mse_full.item()))
 
-    # ---- roofline of the dominant kernel: the sort-means search launch
-    # (search_kernel, used for K > 32; smaller K run one fused launch per
-    # step), timed per launch with events on its stream.  Algorithmic bytes
-    # per color and iteration: 4 (key) + 4 (count) + 1 (membership read) +
-    # 1 (membership write).
+    # ---- roofline of the dominant kernel: the sort-means search launch at
+    # K = 256 (search_kernel<true, true>; K = 64 uses the variant without
+    # deferred scans and K <= 32 one fused launch per step), timed per launch
+    # with events the runtime records at the kernel.  Algorithmic bytes per
+    # color and iteration: 4 (key) + 4 (count) + 1 (membership read) + 1 (write).
     launches = []
     for K in Ks:
-        if K <= 32:
+        if K < 128:
             continue
         st, mse, pal = out[K]
         with wsm.kernel_timer("search", capacity=MAX_ITERS) as kt:
@@ -249,7 +249,7 @@ def main():
     traffic = None
     if SEARCH_TRAFFIC_BYTES is not None and kernel_sources_hash() == SEARCH_TRAFFIC_SRC:
         traffic = SEARCH_TRAFFIC_BYTES
-    roofline = dict(kernel="wsm::search_kernel<true>", bound="hbm", achieved=achieved,
+    roofline = dict(kernel="wsm::search_kernel<true, true>", bound="hbm", achieved=achieved,
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                     traffic_unit="bytes per launch", avg_launch_us=dur_ms * 1e3,
                     launches=len(launches), bytes_per_launch=bytes_per_launch)

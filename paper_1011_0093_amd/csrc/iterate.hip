@@ -243,14 +243,31 @@ __device__ __forceinline__ void prefetch_points(const IterArgs &a, uint32_t (&ke
 // key/cnt/pm.  Sort-means over the LDS copy Ms of M, or full
 // search for the comparator (Ms unused).  Adds the block's sums into totals
 // slot i % 3 and writes its SSE and evaluation partials.
-template <bool PACKED, bool FULL>
+// Deferred sort-means scans: lanes scan kLaneCap entries on their own; a
+// point whose scan is still open then goes to an LDS queue (while it has
+// room; otherwise the lane carries on) and is finished after the block's
+// passes by a whole wave (sm_finish_wave), so that the rare long scans do not
+// hold their wave for their full length.  The queue is kept short because in
+// the first iterations, when every point starts from center 0, most scans
+// are long.  The deferral costs registers, so it is compiled only into the
+// search kernel used for K >= kDeferMinK, where the long scans occur.
+struct DeferQueue {
+    uint32_t n;
+    uint32_t idx[kDeferCap];    // point index
+    uint32_t bd[kDeferCap];     // best distance so far (float bits)
+    uint32_t pjb[kDeferCap];    // next entry << 16 | previous center << 8 | best center
+};
+
+template <bool PACKED, bool FULL, bool DEFER>
 __device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const uint8_t *Ms,
                              unsigned long long *acc, double *dscr, unsigned long long *uscr,
-                             uint32_t (&key)[kCpt], uint32_t (&cnt)[kCpt], int (&pm)[kCpt]) {
+                             DeferQueue *dq, uint32_t (&key)[kCpt], uint32_t (&cnt)[kCpt],
+                             int (&pm)[kCpt]) {
     constexpr int NT = kSearchThreads;
     constexpr int NW = NT / 64;
     constexpr int NACC = PACKED ? 2 : 4;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const int wave = tid >> 6;
     const int rs = lds_row_stride(a.k);
     const int64_t ns = block_slots(a);
@@ -278,16 +295,71 @@ __device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const 
             unpack_key(key[r], x, y, z);
             float bd = 0.f;
             int best = 0;
+            bool done = true;
             if (FULL) {
                 if (valid) best = full_scan(x, y, z, pm[r], a.k, cen, bd, ev);
-            } else {
+            } else if (!DEFER) {
                 if (valid) best = sm_scan(x, y, z, pm[r], a.k, cen, Ms, rs, bd, ev);
+            } else if (valid) {
+                const float thr = sm_scan_begin(x, y, z, pm[r], cen, bd, best, ev);
+                int j = 0, j_end = kLaneCap;
+                for (;;) {
+                    done = sm_scan_range(x, y, z, pm[r], a.k, cen, Ms, rs, thr, j, j_end, bd,
+                                         best, ev);
+                    if (done) break;
+                    const uint32_t q = atomicAdd(&dq->n, 1u);
+                    if (q < (uint32_t)kDeferCap) {
+                        dq->idx[q] = (uint32_t)idx;
+                        dq->bd[q] = __float_as_uint(bd);
+                        dq->pjb[q] = ((uint32_t)j << 16) | ((uint32_t)pm[r] << 8) | (uint32_t)best;
+                        break;
+                    }
+                    j_end = a.k;  // queue full: carry on in place
+                }
             }
-            if (valid) {
+            if (valid && done) {
                 a.sv.m[idx] = (uint8_t)best;
                 sse += (double)cnt[r] * (double)bd;
             }
-            accumulate<PACKED>(acc, best, valid, key[r], cnt[r]);
+            accumulate<PACKED>(acc, best, valid && done, key[r], cnt[r]);
+        }
+    }
+    if (DEFER) {
+        // The deferred scans: wave w takes queue entries w, w + NW, ...
+        __syncthreads();
+        const uint32_t nd = dq->n < (uint32_t)kDeferCap ? dq->n : (uint32_t)kDeferCap;
+        for (uint32_t q = wave; q < nd; q += NW) {
+            const uint32_t idx = dq->idx[q], pjb = dq->pjb[q];
+            const int p = (int)((pjb >> 8) & 0xFFu);
+            int best = (int)(pjb & 0xFFu);
+            float bd = __uint_as_float(dq->bd[q]);
+            uint32_t k, c;
+            load_point(a.pts, idx, k, c);
+            float x, y, z;
+            unpack_key(k, x, y, z);
+            const float4 cp = cen[p];
+            const float thr = sq_dist(x, y, z, cp.x, cp.y, cp.z) * kBreakScale;
+            uint32_t sev = 0;
+            sm_finish_wave(x, y, z, p, a.k, cen, Ms, rs, thr, (int)(pjb >> 16), bd, best, sev);
+            // one lane records the result (stores and LDS atomics only)
+            const bool me = lane == 0;
+            ev += me ? sev : 0u;
+            sse += me ? (double)c * (double)bd : 0.0;
+            if (me) {
+                a.sv.m[idx] = (uint8_t)best;
+                const unsigned long long cc = c;
+                const unsigned long long rr = (k >> 16) & 0xFFu, gg = (k >> 8) & 0xFFu,
+                                         bb = k & 0xFFu;
+                if (PACKED) {
+                    atomicAdd(&acc[best * 2 + 0], cc * rr | ((cc * gg) << 32));
+                    atomicAdd(&acc[best * 2 + 1], cc * bb | (cc << 32));
+                } else {
+                    atomicAdd(&acc[best * 4 + 0], cc * rr);
+                    atomicAdd(&acc[best * 4 + 1], cc * gg);
+                    atomicAdd(&acc[best * 4 + 2], cc * bb);
+                    atomicAdd(&acc[best * 4 + 3], cc);
+                }
+            }
         }
     }
     __syncthreads();
@@ -326,11 +398,12 @@ __global__ __launch_bounds__(kSortThreads) void rows_kernel(IterArgs a, int i) {
 
 // Sort-means step i, second launch: every block copies the centers and M
 // into LDS and searches its chunk.
-template <bool PACKED>
+template <bool PACKED, bool DEFER>
 __global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int i) {
     __shared__ float4 cen[kMaxK];
     __shared__ unsigned long long acc[kMaxK * 4];
     __shared__ __align__(16) uint8_t Ms[kMaxK * kRowStride];
+    __shared__ DeferQueue dq;
     __shared__ double dscr[kSearchThreads / 64];
     __shared__ unsigned long long uscr[kSearchThreads / 64];
     constexpr int NT = kSearchThreads;
@@ -345,8 +418,9 @@ __global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int 
     for (int c = tid; c < a.k; c += NT) cen[c] = pal[c];
     load_rows<NT>(a.sv.rows, a.k, Ms);
     for (int c = tid; c < a.k * NACC; c += NT) acc[c] = 0ull;
+    if (tid == 0) dq.n = 0u;
     __syncthreads();
-    search_chunk<PACKED, false>(a, i, cen, Ms, acc, dscr, uscr, key, cnt, pm);
+    search_chunk<PACKED, false, DEFER>(a, i, cen, Ms, acc, dscr, uscr, &dq, key, cnt, pm);
 }
 
 // Rows of M for palette slot 0 of the state (the pixel map's palette).
@@ -406,7 +480,7 @@ __global__ __launch_bounds__(kSearchThreads) void fused_step_kernel(IterArgs a, 
         Ms[p * lds_row_stride(K) + r] = (uint8_t)t;
     }
     __syncthreads();
-    search_chunk<PACKED, false>(a, i, cen, Ms, acc, dscr, uscr, key, cnt, pm);
+    search_chunk<PACKED, false, false>(a, i, cen, Ms, acc, dscr, uscr, nullptr, key, cnt, pm);
 }
 
 // Full-search comparator: one launch per step, the update applied
@@ -431,7 +505,7 @@ __global__ __launch_bounds__(kSearchThreads) void full_step_kernel(IterArgs a, i
     }
     for (int c = tid; c < a.k * NACC; c += NT) acc[c] = 0ull;
     __syncthreads();
-    search_chunk<PACKED, true>(a, i, cen, nullptr, acc, dscr, uscr, key, cnt, pm);
+    search_chunk<PACKED, true, false>(a, i, cen, nullptr, acc, dscr, uscr, nullptr, key, cnt, pm);
 }
 
 // Final update after the last step of a call (one block).  Publishes the
@@ -654,8 +728,10 @@ static int launch_steps(const IterArgs &a, int max_iters, bool full, hipStream_t
         } else {
             WSM_LAUNCH(WSM_KERNEL_ROWS, rows_kernel<PACKED>, dim3(a.k), dim3(kSortThreads), stream,
                        a, i);
-            WSM_LAUNCH(WSM_KERNEL_SEARCH, search_kernel<PACKED>, dim3(a.grid),
-                       dim3(kSearchThreads), stream, a, i);
+            const auto search = a.k >= kDeferMinK ? search_kernel<PACKED, true>
+                                                  : search_kernel<PACKED, false>;
+            WSM_LAUNCH(WSM_KERNEL_SEARCH, search, dim3(a.grid), dim3(kSearchThreads), stream, a,
+                       i);
         }
     }
     final_kernel<PACKED><<<dim3(1), dim3(kRowThreads), 0, stream>>>(a, max_iters);

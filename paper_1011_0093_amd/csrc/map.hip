@@ -5,8 +5,8 @@
 //   assign  a sort-means scan of every unique color against the final palette,
 //           starting from the color's last membership, over an LDS copy of M
 //           (sm_block.h).  The palette index is scattered into a 2^24-entry
-//           byte table at the color's key; count * distance is summed per
-//           block for the MSE.
+//           byte table laid out in 4 x 4 x 4 color cells (lut_index);
+//           count * distance is summed per block for the MSE.
 //   gather  16 pixels per lane: three 16-byte loads, 16 table lookups, one
 //           16-byte store of indices (and 48 bytes of rounded palette colors
 //           when asked for).  Block 0 also sums the MSE partials.
@@ -18,6 +18,18 @@ int wsm_internal_palette_rows(void *state, int k, hipStream_t stream);
 namespace wsm {
 
 constexpr int kMapThreads = 256;
+
+// Position of color (r, g, b) in the lookup table: the table is laid out in
+// 4 x 4 x 4 color cells of 64 bytes each, so that similar colors share cache
+// lines and the part of the table an image touches stays small.
+__device__ __forceinline__ uint32_t lut_index(uint32_t r, uint32_t g, uint32_t b) {
+    const uint32_t cell = ((r >> 2) << 12) | ((g >> 2) << 6) | (b >> 2);
+    return (cell << 6) | ((r & 3u) << 4) | ((g & 3u) << 2) | (b & 3u);
+}
+
+__device__ __forceinline__ uint32_t lut_index_key(uint32_t key) {
+    return lut_index((key >> 16) & 0xFFu, (key >> 8) & 0xFFu, key & 0xFFu);
+}
 constexpr int kGatherPpt = 16;
 
 __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
@@ -61,7 +73,7 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
             if (valid) {
                 float bd;
                 const int best = sm_scan(x, y, z, pm[r], K, cen, Ms, rs, bd, ev);
-                lut[key[r]] = (uint8_t)best;
+                lut[lut_index_key(key[r])] = (uint8_t)best;
                 acc += (double)cnt[r] * (double)bd;
             }
         }
@@ -112,7 +124,7 @@ __global__ __launch_bounds__(kMapThreads) void map_gather_kernel(
             const uint32_t r = (w[byte >> 2] >> (8 * (byte & 3))) & 0xFFu;
             const uint32_t g = (w[(byte + 1) >> 2] >> (8 * ((byte + 1) & 3))) & 0xFFu;
             const uint32_t b = (w[(byte + 2) >> 2] >> (8 * ((byte + 2) & 3))) & 0xFFu;
-            const uint32_t id = lut[(r << 16) | (g << 8) | b];
+            const uint32_t id = lut[lut_index(r, g, b)];
             idx4[j >> 2] |= id << (8 * (j & 3));
             if (rgb_out) {
                 const uint32_t c = rpal[id];
@@ -136,7 +148,7 @@ __global__ __launch_bounds__(kMapThreads) void map_gather_kernel(
             const int64_t q = first + j;
             if (q >= n) break;
             const uint8_t *px = rgb + q * 3;
-            const uint32_t id = lut[((uint32_t)px[0] << 16) | ((uint32_t)px[1] << 8) | (uint32_t)px[2]];
+            const uint32_t id = lut[lut_index(px[0], px[1], px[2])];
             index_out[q] = (uint8_t)id;
             if (rgb_out) {
                 const uint32_t c = rpal[id];

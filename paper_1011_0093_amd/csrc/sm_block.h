@@ -20,6 +20,9 @@ constexpr int kCpt = 4;                          // points per thread per pass
 constexpr int kPass = kSearchThreads * kCpt;     // points per pass (4096)
 constexpr int kRowStride = kMaxK;                // bytes per row of M in device memory
 constexpr int kScanBatch = 8;                    // row entries fetched per scan step
+constexpr int kLaneCap = 32;                     // entries a lane scans before deferring
+constexpr int kDeferCap = 64;                    // deferred scans per block
+constexpr int kDeferMinK = 128;                  // smallest K whose search defers
 constexpr int kFusedMaxK = 32;                   // largest K sorted inside the search block
 
 // LDS row stride for K centers: K - 1 entries rounded up to 16 bytes.
@@ -124,11 +127,67 @@ __device__ __forceinline__ void load_rows(const uint8_t *__restrict__ M, int K, 
 // Sort-means scan (Alg. 2, inner loop) of point x from its previous center
 // p over the LDS copy of M: starting from d(x, c_p), centers are taken in row
 // order until the first t with d(c_p, c_t)^2 >= thr = 4 (1 + 2^-16) d(x, c_p)^2.
-// Entries are fetched kScanBatch at a time (one 8-byte LDS read of the row,
-// the center reads issued together) and then taken in order; distances
-// computed past the stop are discarded.  Reads past the row's K - 1 entries
-// stay inside the LDS row (its stride is a multiple of 16) and the center
-// table.
+//
+// sm_scan_range takes the row entries [j, min(j_end, K - 1)) in batches of
+// kScanBatch (one 8-byte LDS read of the row, the center reads issued
+// together, then the entries taken in order; distances computed past the
+// stop are discarded) and returns whether the scan has ended (stop found or
+// row exhausted); j is left at the next batch.  Reads past the row's K - 1
+// entries stay inside the LDS row (its stride is a multiple of 16) and the
+// center table.
+__device__ __forceinline__ bool sm_scan_range(float x, float y, float z, int p, int K,
+                                              const float4 *cen, const uint8_t *Ms, int rs,
+                                              float thr, int &j, int j_end, float &bd, int &best,
+                                              uint32_t &ev) {
+    const float4 cp = cen[p];
+    const uint8_t *row = Ms + p * rs;
+    const int n = K - 1;
+    const int jm = j_end < n ? j_end : n;
+    for (; j < jm; j += kScanBatch) {
+        const uint2 w8 = *(const uint2 *)(row + j);
+        float dpt[kScanBatch], d[kScanBatch];
+        int t[kScanBatch];
+#pragma unroll
+        for (int e = 0; e < kScanBatch; ++e) {
+            t[e] = ((e < 4 ? w8.x : w8.y) >> (8 * (e & 3))) & 0xFFu;
+            const float4 ct = cen[t[e]];
+            dpt[e] = sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z);
+            d[e] = sq_dist(x, y, z, ct.x, ct.y, ct.z);
+        }
+        bool stop = false;
+#pragma unroll
+        for (int e = 0; e < kScanBatch; ++e) {
+            if (!stop) {
+                if (j + e >= n || dpt[e] >= thr) {
+                    stop = true;
+                } else {
+                    ev += 1;
+                    if (better_center(d[e], bd, t[e], best, p)) {
+                        bd = d[e];
+                        best = t[e];
+                    }
+                }
+            }
+        }
+        if (stop) return true;
+    }
+    return j >= n;
+}
+
+// The threshold of point x with previous center p; starts the scan state.
+__device__ __forceinline__ float sm_scan_begin(float x, float y, float z, int p,
+                                               const float4 *cen, float &bd, int &best,
+                                               uint32_t &ev) {
+    const float4 cp = cen[p];
+    const float prev = sq_dist(x, y, z, cp.x, cp.y, cp.z);
+    bd = prev;
+    best = p;
+    ev += 1;
+    return prev * kBreakScale;
+}
+
+// The whole scan of one point (the same steps as sm_scan_begin followed by
+// sm_scan_range over the whole row, in one loop).
 __device__ __forceinline__ int sm_scan(float x, float y, float z, int p, int K,
                                        const float4 *cen, const uint8_t *Ms, int rs,
                                        float &best_d, uint32_t &ev) {
@@ -170,6 +229,47 @@ __device__ __forceinline__ int sm_scan(float x, float y, float z, int p, int K,
     }
     best_d = bd;
     return best;
+}
+
+// Order key of a candidate under the tie rule (dist, k != p, k): smaller is
+// better.  Distances are non-negative, so their bits order like the values.
+__device__ __forceinline__ unsigned long long scan_key(float d, int t, int p) {
+    return ((unsigned long long)__float_as_uint(d) << 32) | (unsigned)(t == p ? 0 : 256 + t);
+}
+
+// The rest of one point's scan, from row entry j, by the whole wave: lane l
+// takes entry j + l, the stop is the first entry (in row order) at or past
+// the threshold, and the entries before it are reduced with scan_key.  Every
+// argument is the same in all lanes, and all 64 lanes must call it; the
+// results (bd, best, evaluations made) are the same in all lanes.
+__device__ __forceinline__ void sm_finish_wave(float x, float y, float z, int p, int K,
+                                               const float4 *cen, const uint8_t *Ms, int rs,
+                                               float thr, int j, float &bd, int &best,
+                                               uint32_t &evals) {
+    const int lane = threadIdx.x & 63;
+    const int n = K - 1;
+    const float4 cp = cen[p];
+    const uint8_t *row = Ms + p * rs;
+    unsigned long long bk = scan_key(bd, best, p);
+    uint32_t sev = 0;
+    for (int jb = j; jb < n; jb += 64) {
+        const int jj = jb + lane;
+        const bool in = jj < n;
+        const int t = in ? row[jj] : 0;
+        const float4 ct = cen[t];
+        const float dpt = sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z);
+        const float d = sq_dist(x, y, z, ct.x, ct.y, ct.z);
+        const unsigned long long smask = __ballot(!in || dpt >= thr);
+        const int first = smask != 0ull ? __builtin_ctzll(smask) : 64;
+        const bool ok = lane < first;
+        sev += (uint32_t)__popcll(__ballot(ok));
+        const unsigned long long k = wave_last_u64(wave_min_u64(ok ? scan_key(d, t, p) : ~0ull));
+        bk = k < bk ? k : bk;
+        if (first < 64) break;
+    }
+    bd = __uint_as_float((uint32_t)(bk >> 32));
+    best = (bk & 0x100ull) ? (int)(bk & 0xFFull) : p;
+    evals = sev;
 }
 
 // Full search over all K centers with the same tie key.

@@ -165,6 +165,32 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
+// Minimum over the wave; the result is valid in lane 63.
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long t;
+    t = dpp_u64<kDppRowShr1>(v);
+    if (dpp_takes<kDppRowShr1>(lane) && t < v) v = t;
+    t = dpp_u64<kDppRowShr2>(v);
+    if (dpp_takes<kDppRowShr2>(lane) && t < v) v = t;
+    t = dpp_u64<kDppRowShr4>(v);
+    if (dpp_takes<kDppRowShr4>(lane) && t < v) v = t;
+    t = dpp_u64<kDppRowShr8>(v);
+    if (dpp_takes<kDppRowShr8>(lane) && t < v) v = t;
+    t = dpp_u64<kDppRowBcast15>(v);
+    if (dpp_takes<kDppRowBcast15>(lane) && t < v) v = t;
+    t = dpp_u64<kDppRowBcast31>(v);
+    if (dpp_takes<kDppRowBcast31>(lane) && t < v) v = t;
+    return v;
+}
+
+// Value of lane 63 broadcast to the wave (scalar reads).
+__device__ __forceinline__ unsigned long long wave_last_u64(unsigned long long v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 // Value of lane 63 broadcast to the wave (scalar read).
 __device__ __forceinline__ uint32_t wave_last_u32(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
