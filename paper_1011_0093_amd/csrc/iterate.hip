@@ -412,11 +412,16 @@ __global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int 
     uint32_t key[kCpt], cnt[kCpt];
     int pm[kCpt];
     prefetch_points(a, key, cnt, pm);
+    // This step's centers and rows are fetched before the record is read, so
+    // the loads overlap (they are only used if the loop has not stopped).
+    const float4 *pal = a.sv.pal + (size_t)((i + 1) & 1) * kMaxK;
+    const float4 pc = tid < a.k ? pal[tid] : make_float4(0.f, 0.f, 0.f, 0.f);
+    RowRegs<NT> R;
+    fetch_rows<NT>(a.sv.rows, a.k, R);
     const Record rec = a.sv.hdr->rec[(i + 1) & 1];
     if (rec.converged) return;
-    const float4 *pal = a.sv.pal + (size_t)((i + 1) & 1) * kMaxK;
-    for (int c = tid; c < a.k; c += NT) cen[c] = pal[c];
-    load_rows<NT>(a.sv.rows, a.k, Ms);
+    if (tid < a.k) cen[tid] = pc;
+    store_rows<NT>(R, a.k, Ms);
     for (int c = tid; c < a.k * NACC; c += NT) acc[c] = 0ull;
     if (tid == 0) dq.n = 0u;
     __syncthreads();

@@ -96,32 +96,50 @@ __device__ void sort_row(const float4 *cen, int K, int p, unsigned long long *__
 }
 
 // Copy the K rows of M (device layout, kRowStride bytes per row) into LDS
-// rows of lds_row_stride(K) bytes.  All threads of the block call it.
-// All of a thread's loads are issued before the first LDS store.
+// rows of lds_row_stride(K) bytes: fetch_rows issues a thread's loads into
+// registers, store_rows writes them to LDS.  All threads of the block call
+// both.
 template <int NT>
-__device__ __forceinline__ void load_rows(const uint8_t *__restrict__ M, int K, uint8_t *Ms) {
-    constexpr int kRegs = (kMaxK * kRowStride / 16 + NT - 1) / NT;
+struct RowRegs {
+    static constexpr int kRegs = (kMaxK * kRowStride / 16 + NT - 1) / NT;
+    uint4 v[kRegs];
+};
+
+template <int NT>
+__device__ __forceinline__ void fetch_rows(const uint8_t *__restrict__ M, int K, RowRegs<NT> &R) {
+    const int per_row = lds_row_stride(K) / 16;
+    const int nq = K * per_row;
+#pragma unroll
+    for (int u = 0; u < RowRegs<NT>::kRegs; ++u) {
+        const int q = threadIdx.x + u * NT;
+        R.v[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (q < nq) {
+            const int r = q / per_row, c = q - r * per_row;
+            R.v[u] = *(const uint4 *)(M + (size_t)r * kRowStride + c * 16);
+        }
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void store_rows(const RowRegs<NT> &R, int K, uint8_t *Ms) {
     const int rs = lds_row_stride(K);
     const int per_row = rs / 16;
     const int nq = K * per_row;
-    uint4 v[kRegs];
 #pragma unroll
-    for (int u = 0; u < kRegs; ++u) {
-        const int q = threadIdx.x + u * NT;
-        v[u] = make_uint4(0u, 0u, 0u, 0u);
-        if (q < nq) {
-            const int r = q / per_row, c = q - r * per_row;
-            v[u] = *(const uint4 *)(M + (size_t)r * kRowStride + c * 16);
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < kRegs; ++u) {
+    for (int u = 0; u < RowRegs<NT>::kRegs; ++u) {
         const int q = threadIdx.x + u * NT;
         if (q < nq) {
             const int r = q / per_row, c = q - r * per_row;
-            *(uint4 *)(Ms + r * rs + c * 16) = v[u];
+            *(uint4 *)(Ms + r * rs + c * 16) = R.v[u];
         }
     }
+}
+
+template <int NT>
+__device__ __forceinline__ void load_rows(const uint8_t *__restrict__ M, int K, uint8_t *Ms) {
+    RowRegs<NT> R;
+    fetch_rows<NT>(M, K, R);
+    store_rows<NT>(R, K, Ms);
 }
 
 // Sort-means scan (Alg. 2, inner loop) of point x from its previous center
@@ -150,7 +168,7 @@ __device__ __forceinline__ bool sm_scan_range(float x, float y, float z, int p, 
 #pragma unroll
         for (int e = 0; e < kScanBatch; ++e) {
             t[e] = ((e < 4 ? w8.x : w8.y) >> (8 * (e & 3))) & 0xFFu;
-            const float4 ct = cen[t[e]];
+            const float3 ct = *(const float3 *)(cen + t[e]);  // the 4th lane is unused
             dpt[e] = sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z);
             d[e] = sq_dist(x, y, z, ct.x, ct.y, ct.z);
         }
@@ -206,7 +224,7 @@ __device__ __forceinline__ int sm_scan(float x, float y, float z, int p, int K,
 #pragma unroll
         for (int e = 0; e < kScanBatch; ++e) {
             t[e] = ((e < 4 ? w8.x : w8.y) >> (8 * (e & 3))) & 0xFFu;
-            const float4 ct = cen[t[e]];
+            const float3 ct = *(const float3 *)(cen + t[e]);  // the 4th lane is unused
             dpt[e] = sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z);
             d[e] = sq_dist(x, y, z, ct.x, ct.y, ct.z);
         }
