@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/search_kernel_512x512_traffic.md).  It describes the kernel
 # sources it was measured on (hash below); for any other sources the bench
 # reports null.
-SEARCH_TRAFFIC_BYTES = 3064495
-SEARCH_TRAFFIC_SRC = "21ad572e052939b3"
+SEARCH_TRAFFIC_BYTES = 5611423
+SEARCH_TRAFFIC_SRC = "532b0be4bbd50c6a"
 _KERNEL_SOURCES = ("iterate.hip", "sm_block.h", "wave_ops.h", "wsm_internal.h")
 
 
