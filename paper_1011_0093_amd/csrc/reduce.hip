@@ -293,16 +293,22 @@ __global__ __launch_bounds__(kCompactThreads) void reduce_compact_kernel(
         return;
     }
     uint32_t o = (uint32_t)s_excl + local;
-    for (int j = 0; j < kBinsPerWave; j += 64) {
-        const int bin = wave * kBinsPerWave + j + lane;
-        const uint32_t c = hist[bin];
-        const unsigned long long m = __ballot(c != 0u);
-        if (c != 0u) {
-            const uint32_t pos = o + (uint32_t)__popcll(m & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
-            colors[pos] = ((uint32_t)s << kSliceBits) | (uint32_t)bin;
-            counts[pos] = c;
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int j = 0; j < kBinsPerWave; j += 64 * 4) {
+        uint32_t c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = wb[j + 64 * u + lane];  // reads issued together
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int bin = wave * kBinsPerWave + j + 64 * u + lane;
+            const unsigned long long m = __ballot(c[u] != 0u);
+            if (c[u] != 0u) {
+                const uint32_t pos = o + (uint32_t)__popcll(m & below);
+                colors[pos] = ((uint32_t)s << kSliceBits) | (uint32_t)bin;
+                counts[pos] = c[u];
+            }
+            o += (uint32_t)__popcll(m);
         }
-        o += (uint32_t)__popcll(m);
     }
 }
 
