@@ -163,6 +163,48 @@ def test_lockstep_medium(K):
     print(stats[-1])
 
 
+@pytest.mark.parametrize("K", [128, 256])
+def test_lockstep_small_many_centers(K):
+    """K = 128 is the first K whose search defers long scans; on the small
+    image (about 28k colors) every block is short, and the first iteration
+    (all colors start at center 0) fills the deferral queues."""
+    img = synth.workload_image("small", 1)
+    _say("lockstep small seed 1 K", K)
+    stats = _lockstep(img, K, 1, 4)
+    print(stats[-1])
+
+
+def test_lockstep_tiny_table_k256():
+    """A table of a few hundred colors with K = 256: two search blocks, rows
+    of 255 entries, most clusters holding one or two colors."""
+    rng = np.random.default_rng(11)
+    img = rng.integers(0, 256, size=(24, 20, 3)).astype(np.uint8)
+    img[:, :4] = img[:1, :4]          # some repeated colors
+    _say("lockstep tiny random image 24x20 K 256")
+    stats = _lockstep(img, 256, 5, 3)
+    print(stats[-1])
+
+
+@pytest.mark.parametrize("K", [64, 256])
+def test_sort_means_on_raw_pixels_equals_weighted_colors(K):
+    """Sort-means run directly on every pixel (weight 1) gives bit-identical
+    palettes to sort-means on the weighted unique colors (the exact integer
+    sums make Sec. 2's data reduction and weighting exact on the GPU too)."""
+    wsm = _wsm()
+    img = synth.workload_image("small", 0)
+    _say("sort-means on pixels vs colors small seed 0 K", K)
+    g = _gpu_img(img)
+    col, cnt = wsm.reduce_colors(g)
+    n_pix = img.shape[0] * img.shape[1]
+    pal = wsm.palette_from_indices(col, synth.init_indices(2, col.numel(), K))
+    a = wsm.init(col, cnt, n_pix, pal)
+    a.iterate(8, 0.0)
+    b = wsm.init_pixels(g, pal)
+    b.iterate(8, 0.0)
+    assert torch.equal(a.palette().cpu(), b.palette().cpu())
+    np.testing.assert_allclose(a.history()[0], b.history()[0], rtol=1e-12)
+
+
 def test_lockstep_full_search_comparator():
     img = synth.workload_image("small", 2)
     _say("lockstep small seed 2 K=32 full search")
