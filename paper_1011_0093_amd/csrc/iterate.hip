@@ -238,11 +238,6 @@ __device__ __forceinline__ void prefetch_points(const IterArgs &a, uint32_t (&ke
     }
 }
 
-// Search and accumulation over a block's points (block_slots), in passes of
-// kPass (kCpt points per thread); the first pass's points are already in
-// key/cnt/pm.  Sort-means over the LDS copy Ms of M, or full
-// search for the comparator (Ms unused).  Adds the block's sums into totals
-// slot i % 3 and writes its SSE and evaluation partials.
 // Deferred sort-means scans: lanes scan kLaneCap entries on their own; a
 // point whose scan is still open then goes to an LDS queue (while it has
 // room; otherwise the lane carries on) and is finished after the block's
@@ -258,11 +253,13 @@ struct DeferQueue {
     uint32_t pjb[kDeferCap];    // next entry << 16 | previous center << 8 | best center
 };
 
-template <bool PACKED, bool FULL, bool DEFER>
-__device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const uint8_t *Ms,
+// End of a search block: finishes the deferred scans (DEFER), adds the
+// block's sums into totals slot i % 3 and writes its SSE and evaluation
+// partials.  All threads call it.
+template <bool PACKED, bool DEFER>
+__device__ void finish_block(const IterArgs &a, int i, const float4 *cen, const uint8_t *Ms,
                              unsigned long long *acc, double *dscr, unsigned long long *uscr,
-                             DeferQueue *dq, uint32_t (&key)[kCpt], uint32_t (&cnt)[kCpt],
-                             int (&pm)[kCpt]) {
+                             DeferQueue *dq, double sse, uint32_t ev) {
     constexpr int NT = kSearchThreads;
     constexpr int NW = NT / 64;
     constexpr int NACC = PACKED ? 2 : 4;
@@ -270,60 +267,6 @@ __device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const 
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int rs = lds_row_stride(a.k);
-    const int64_t ns = block_slots(a);
-    double sse = 0.0;
-    uint32_t ev = 0;
-    for (int64_t s0 = 0; s0 < ns; s0 += kCpt * NW) {
-        if (s0 != 0) {
-#pragma unroll
-            for (int r = 0; r < kCpt; ++r) {
-                const int64_t slot = s0 + r * NW + wave;
-                const int64_t idx = slot_point(a, slot);
-                if (slot < ns && idx < a.pts.n) {
-                    load_point(a.pts, idx, key[r], cnt[r]);
-                    pm[r] = a.sv.m[idx];
-                }
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < kCpt; ++r) {
-            if (s0 + r * NW >= ns) break;  // block-uniform
-            const int64_t slot = s0 + r * NW + wave;
-            const int64_t idx = slot_point(a, slot);
-            const bool valid = slot < ns && idx < a.pts.n;
-            float x, y, z;
-            unpack_key(key[r], x, y, z);
-            float bd = 0.f;
-            int best = 0;
-            bool done = true;
-            if (FULL) {
-                if (valid) best = full_scan(x, y, z, pm[r], a.k, cen, bd, ev);
-            } else if (!DEFER) {
-                if (valid) best = sm_scan(x, y, z, pm[r], a.k, cen, Ms, rs, bd, ev);
-            } else if (valid) {
-                const float thr = sm_scan_begin(x, y, z, pm[r], cen, bd, best, ev);
-                int j = 0, j_end = kLaneCap;
-                for (;;) {
-                    done = sm_scan_range(x, y, z, pm[r], a.k, cen, Ms, rs, thr, j, j_end, bd,
-                                         best, ev);
-                    if (done) break;
-                    const uint32_t q = atomicAdd(&dq->n, 1u);
-                    if (q < (uint32_t)kDeferCap) {
-                        dq->idx[q] = (uint32_t)idx;
-                        dq->bd[q] = __float_as_uint(bd);
-                        dq->pjb[q] = ((uint32_t)j << 16) | ((uint32_t)pm[r] << 8) | (uint32_t)best;
-                        break;
-                    }
-                    j_end = a.k;  // queue full: carry on in place
-                }
-            }
-            if (valid && done) {
-                a.sv.m[idx] = (uint8_t)best;
-                sse += (double)cnt[r] * (double)bd;
-            }
-            accumulate<PACKED>(acc, best, valid && done, key[r], cnt[r]);
-        }
-    }
     if (DEFER) {
         // The deferred scans: wave w takes queue entries w, w + NW, ...
         __syncthreads();
@@ -376,6 +319,88 @@ __device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const 
     }
 }
 
+// Search and accumulation over a block's points (block_slots), in passes of
+// kPass (kCpt points per thread); the first pass's points are already in
+// key/cnt/pm.  Sort-means over the LDS copy Ms of M, or full
+// search for the comparator (Ms unused).  Adds the block's sums into totals
+// slot i % 3 and writes its SSE and evaluation partials.
+
+template <bool PACKED, bool FULL, bool DEFER>
+__device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const uint8_t *Ms,
+                             unsigned long long *acc, double *dscr, unsigned long long *uscr,
+                             DeferQueue *dq, uint32_t (&key)[kCpt], uint32_t (&cnt)[kCpt],
+                             int (&pm)[kCpt], bool first = false) {
+    constexpr int NT = kSearchThreads;
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int rs = lds_row_stride(a.k);
+    const int64_t ns = block_slots(a);
+    double sse = 0.0;
+    uint32_t ev = 0;
+    for (int64_t s0 = 0; s0 < ns; s0 += kCpt * NW) {
+        if (s0 != 0) {
+#pragma unroll
+            for (int r = 0; r < kCpt; ++r) {
+                const int64_t slot = s0 + r * NW + wave;
+                const int64_t idx = slot_point(a, slot);
+                if (slot < ns && idx < a.pts.n) {
+                    load_point(a.pts, idx, key[r], cnt[r]);
+                    pm[r] = a.sv.m[idx];
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kCpt; ++r) {
+            if (s0 + r * NW >= ns) break;  // block-uniform
+            const int64_t slot = s0 + r * NW + wave;
+            const int64_t idx = slot_point(a, slot);
+            const bool valid = slot < ns && idx < a.pts.n;
+            float x, y, z;
+            unpack_key(key[r], x, y, z);
+            float bd = 0.f;
+            int best = 0;
+            bool done = true;
+            if (FULL) {
+                if (valid) best = full_scan(x, y, z, pm[r], a.k, cen, bd, ev);
+            } else if (first) {
+                // first step (every point starts from center 0, whose whole row
+                // is scanned): the full search gives the same center, and the
+                // scan's evaluation count comes from a binary search of row p
+                if (valid) {
+                    uint32_t unused = 0;
+                    best = full_scan(x, y, z, pm[r], a.k, cen, bd, unused);
+                    ev += sm_scan_evals(x, y, z, pm[r], a.k, cen, Ms, rs);
+                }
+            } else if (!DEFER) {
+                if (valid) best = sm_scan(x, y, z, pm[r], a.k, cen, Ms, rs, bd, ev);
+            } else if (valid) {
+                const float thr = sm_scan_begin(x, y, z, pm[r], cen, bd, best, ev);
+                int j = 0, j_end = kLaneCap;
+                for (;;) {
+                    done = sm_scan_range(x, y, z, pm[r], a.k, cen, Ms, rs, thr, j, j_end, bd,
+                                         best, ev);
+                    if (done) break;
+                    const uint32_t q = atomicAdd(&dq->n, 1u);
+                    if (q < (uint32_t)kDeferCap) {
+                        dq->idx[q] = (uint32_t)idx;
+                        dq->bd[q] = __float_as_uint(bd);
+                        dq->pjb[q] = ((uint32_t)j << 16) | ((uint32_t)pm[r] << 8) | (uint32_t)best;
+                        break;
+                    }
+                    j_end = a.k;  // queue full: carry on in place
+                }
+            }
+            if (valid && done) {
+                a.sv.m[idx] = (uint8_t)best;
+                sse += (double)cnt[r] * (double)bd;
+            }
+            accumulate<PACKED>(acc, best, valid && done, key[r], cnt[r]);
+        }
+    }
+    finish_block<PACKED, DEFER>(a, i, cen, Ms, acc, dscr, uscr, dq, sse, ev);
+}
+
 // Sort-means step i, first launch: the update of step i-1 in every block
 // (see the file comment), then block p sorts row p of M for the new
 // centers.  Block 0 clears the totals slot step i accumulates into.
@@ -398,7 +423,7 @@ __global__ __launch_bounds__(kSortThreads) void rows_kernel(IterArgs a, int i) {
 
 // Sort-means step i, second launch: every block copies the centers and M
 // into LDS and searches its chunk.
-template <bool PACKED, bool DEFER>
+template <bool PACKED, bool DEFER, bool FIRST>
 __global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int i) {
     __shared__ float4 cen[kMaxK];
     __shared__ unsigned long long acc[kMaxK * 4];
@@ -425,7 +450,10 @@ __global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int 
     for (int c = tid; c < a.k * NACC; c += NT) acc[c] = 0ull;
     if (tid == 0) dq.n = 0u;
     __syncthreads();
-    search_chunk<PACKED, false, DEFER>(a, i, cen, Ms, acc, dscr, uscr, &dq, key, cnt, pm);
+    // The launch for a call's first step (FIRST) checks whether the state has
+    // completed no step yet, i.e. every membership is still 0 (state init).
+    const bool first = FIRST && rec.iters == 0;
+    search_chunk<PACKED, false, DEFER>(a, i, cen, Ms, acc, dscr, uscr, &dq, key, cnt, pm, first);
 }
 
 // Rows of M for palette slot 0 of the state (the pixel map's palette).
@@ -733,8 +761,9 @@ static int launch_steps(const IterArgs &a, int max_iters, bool full, hipStream_t
         } else {
             WSM_LAUNCH(WSM_KERNEL_ROWS, rows_kernel<PACKED>, dim3(a.k), dim3(kSortThreads), stream,
                        a, i);
-            const auto search = a.k >= kDeferMinK ? search_kernel<PACKED, true>
-                                                  : search_kernel<PACKED, false>;
+            const auto search = i == 0 ? search_kernel<PACKED, false, true>
+                                : a.k >= kDeferMinK ? search_kernel<PACKED, true, false>
+                                                    : search_kernel<PACKED, false, false>;
             WSM_LAUNCH(WSM_KERNEL_SEARCH, search, dim3(a.grid), dim3(kSearchThreads), stream, a,
                        i);
         }

@@ -290,6 +290,28 @@ __device__ __forceinline__ void sm_finish_wave(float x, float y, float z, int p,
     evals = sev;
 }
 
+// The number of evaluations the sort-means scan of x from p makes: 1 (the
+// previous center) + the number of row entries before the first one at or
+// past the threshold.  Row p is sorted by d(c_p, c_t)^2, so a binary search
+// finds that position; the distances are recomputed with the scan's own
+// expression.
+__device__ __forceinline__ uint32_t sm_scan_evals(float x, float y, float z, int p, int K,
+                                                  const float4 *cen, const uint8_t *Ms, int rs) {
+    const float4 cp = cen[p];
+    const float thr = sq_dist(x, y, z, cp.x, cp.y, cp.z) * kBreakScale;
+    const uint8_t *row = Ms + p * rs;
+    int lo = 0, hi = K - 1;  // first entry in [lo, hi] with d >= thr (hi: none)
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const float4 ct = cen[row[mid]];
+        if (sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z) >= thr)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return 1u + (uint32_t)lo;
+}
+
 // Full search over all K centers with the same tie key.
 __device__ __forceinline__ int full_scan(float x, float y, float z, int p, int K,
                                          const float4 *cen, float &best_d, uint32_t &ev) {

@@ -185,14 +185,18 @@ def test_lockstep_tiny_table_k256():
     print(stats[-1])
 
 
-@pytest.mark.parametrize("K", [64, 256])
-def test_sort_means_on_raw_pixels_equals_weighted_colors(K):
+@pytest.mark.parametrize("K,size", [(64, 256), (256, 256), (64, 1024), (256, 1024)])
+def test_sort_means_on_raw_pixels_equals_weighted_colors(K, size):
     """Sort-means run directly on every pixel (weight 1) gives bit-identical
     palettes to sort-means on the weighted unique colors (the exact integer
-    sums make Sec. 2's data reduction and weighting exact on the GPU too)."""
+    sums make Sec. 2's data reduction and weighting exact on the GPU too);
+    at 1024x1024 each block holds several chunks of pixels."""
     wsm = _wsm()
-    img = synth.workload_image("small", 0)
-    _say("sort-means on pixels vs colors small seed 0 K", K)
+    if size == 256:
+        img = synth.workload_image("small", 0)
+    else:
+        img = synth.sinusoid_field_image(1, size, size)
+    _say("sort-means on pixels vs colors", img.shape, "K", K)
     g = _gpu_img(img)
     col, cnt = wsm.reduce_colors(g)
     n_pix = img.shape[0] * img.shape[1]
