@@ -141,8 +141,10 @@ int wsm_iterate_full(const wsm_problem *prob, int max_iters, double eps,
 /* Device pointers into a state.  palette: float4[k] (R,G,B,0) after the
  * last update; membership: uint8[n_points]; sse_history / evals_history:
  * [WSM_HISTORY], entry t-1 for iteration t (SSE_t normalised by n_pixels,
- * i.e. the MSE of the palette entering iteration t; evals = point-center
- * distances computed); info: int32[4] = {iterations done, converged,
+ * i.e. the MSE of the palette entering iteration t; evals = the distance
+ * evaluations of Alg. 2's scan, summed over the points: 1 + the centers
+ * before the break per point for wsm_iterate, k per point for
+ * wsm_iterate_full); info: int32[4] = {iterations done, converged,
  * device error flags, reserved}. */
 typedef struct wsm_views {
     const float *palette;
