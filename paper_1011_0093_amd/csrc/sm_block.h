@@ -6,9 +6,14 @@
 // left out, since the scan starts from the second one.  It is built once per
 // set of centers (sort_row, one block per row) and kept in device memory as
 // K rows of kRowStride bytes; a search block copies the K x (K - 1) bytes
-// into LDS.  The scan recomputes d(c_p, c_t)^2 from the centers in LDS with
-// the same expression the rows were sorted by, so the break test sees
-// bit-equal values.
+// into LDS.  (For K <= kFusedMaxK every search block sorts the rows itself.)
+// The scan recomputes d(c_p, c_t)^2 from the centers in LDS with the same
+// expression the rows were sorted by, so the break test sees bit-equal
+// values.
+//
+// Scans are taken kScanBatch entries at a time.  For K >= kDeferMinK a lane
+// stops after kLaneCap entries and leaves the rest of a long scan to the
+// whole wave (sm_finish_wave), so that one long scan does not hold its wave.
 #pragma once
 
 #include "wave_ops.h"
