@@ -26,7 +26,7 @@ constexpr int kPass = kSearchThreads * kCpt;     // points per pass (4096)
 constexpr int kRowStride = kMaxK;                // bytes per row of M in device memory
 constexpr int kScanBatch = 8;                    // row entries fetched per scan step
 constexpr int kLaneCap = 32;                     // entries a lane scans before deferring
-constexpr int kDeferCap = 64;                    // deferred scans per block
+constexpr int kDeferCap = 512;                   // deferred scans per block
 constexpr int kDeferMinK = 128;                  // smallest K whose search defers
 constexpr int kFusedMaxK = 32;                   // largest K sorted inside the search block
 
