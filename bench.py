@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/search_kernel_512x512_traffic.md).  It describes the kernel
 # sources it was measured on (hash below); for any other sources the bench
 # reports null.
-SEARCH_TRAFFIC_BYTES = 5611423
-SEARCH_TRAFFIC_SRC = "532b0be4bbd50c6a"
+SEARCH_TRAFFIC_BYTES = 5627336
+SEARCH_TRAFFIC_SRC = "721041efa4e85382"
 _KERNEL_SOURCES = ("iterate.hip", "sm_block.h", "wave_ops.h", "wsm_internal.h")
 
 
@@ -229,7 +229,8 @@ def main():
             mse_wsm=float(out[K][1].item()), mse_full=float(mse_full.item()))
 
     # ---- roofline of the dominant kernel: the sort-means search launch at
-    # K = 256 (search_kernel<true, true>; K = 64 uses the variant without
+    # K = 256 from the second step on (search_kernel<true, true, false>; the
+    # first step of a call runs its own variant, K = 64 the variant without
     # deferred scans and K <= 32 one fused launch per step), timed per launch
     # with events the runtime records at the kernel.  Algorithmic bytes per
     # color and iteration: 4 (key) + 4 (count) + 1 (membership read) + 1 (write).
@@ -242,14 +243,14 @@ def main():
             s = wsm.init(col, cnt, N, pal)
             s.iterate(MAX_ITERS, EPS)
         it = s.info()["iters"]
-        launches += kt.ms[:it]
+        launches += kt.ms[1:it]
     dur_ms = float(np.mean(launches))
     bytes_per_launch = 10.0 * n_unique
     achieved = bytes_per_launch / (dur_ms * 1e-3) / 1e9
     traffic = None
     if SEARCH_TRAFFIC_BYTES is not None and kernel_sources_hash() == SEARCH_TRAFFIC_SRC:
         traffic = SEARCH_TRAFFIC_BYTES
-    roofline = dict(kernel="wsm::search_kernel<true, true>", bound="hbm", achieved=achieved,
+    roofline = dict(kernel="wsm::search_kernel<true, true, false>", bound="hbm", achieved=achieved,
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                     traffic_unit="bytes per launch", avg_launch_us=dur_ms * 1e3,
                     launches=len(launches), bytes_per_launch=bytes_per_launch)
