@@ -266,7 +266,7 @@ __device__ void finish_block(const IterArgs &a, int i, const float4 *cen, const 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int rs = lds_row_stride(a.k);
+    const int rs = lds_rows_stride<DEFER>(a.k);
     if (DEFER) {
         // The deferred scans: wave w takes queue entries w, w + NW, ...
         __syncthreads();
@@ -283,7 +283,8 @@ __device__ void finish_block(const IterArgs &a, int i, const float4 *cen, const 
             const float4 cp = cen[p];
             const float thr = sq_dist(x, y, z, cp.x, cp.y, cp.z) * kBreakScale;
             uint32_t sev = 0;
-            sm_finish_wave(x, y, z, p, a.k, cen, Ms, rs, thr, (int)(pjb >> 16), bd, best, sev);
+            const RowView rv{Ms + p * rs, a.sv.rows + (size_t)p * kRowStride, kRowPrefix};
+            sm_finish_wave(x, y, z, p, a.k, cen, rv, thr, (int)(pjb >> 16), bd, best, sev);
             // one lane records the result (stores and LDS atomics only)
             const bool me = lane == 0;
             ev += me ? sev : 0u;
@@ -334,7 +335,7 @@ __device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const 
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
-    const int rs = lds_row_stride(a.k);
+    const int rs = lds_rows_stride<DEFER>(a.k);
     const int64_t ns = block_slots(a);
     double sse = 0.0;
     uint32_t ev = 0;
@@ -376,10 +377,12 @@ __device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const 
                 if (valid) best = sm_scan(x, y, z, pm[r], a.k, cen, Ms, rs, bd, ev);
             } else if (valid) {
                 const float thr = sm_scan_begin(x, y, z, pm[r], cen, bd, best, ev);
+                const RowView rv{Ms + pm[r] * rs, a.sv.rows + (size_t)pm[r] * kRowStride,
+                                 kRowPrefix};
                 int j = 0, j_end = kLaneCap;
                 for (;;) {
-                    done = sm_scan_range(x, y, z, pm[r], a.k, cen, Ms, rs, thr, j, j_end, bd,
-                                         best, ev);
+                    done = sm_scan_range(x, y, z, pm[r], a.k, cen, rv, thr, j, j_end, bd, best,
+                                         ev);
                     if (done) break;
                     const uint32_t q = atomicAdd(&dq->n, 1u);
                     if (q < (uint32_t)kDeferCap) {
@@ -427,7 +430,8 @@ template <bool PACKED, bool DEFER, bool FIRST>
 __global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int i) {
     __shared__ float4 cen[kMaxK];
     __shared__ unsigned long long acc[kMaxK * 4];
-    __shared__ __align__(16) uint8_t Ms[kMaxK * kRowStride];
+    // rows of M: the first kRowPrefix entries when scans defer, else whole
+    __shared__ __align__(16) uint8_t Ms[kMaxK * (DEFER ? kRowPrefix : kRowStride)];
     __shared__ DeferQueue dq;
     __shared__ double dscr[kSearchThreads / 64];
     __shared__ unsigned long long uscr[kSearchThreads / 64];
@@ -442,11 +446,11 @@ __global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int 
     const float4 *pal = a.sv.pal + (size_t)((i + 1) & 1) * kMaxK;
     const float4 pc = tid < a.k ? pal[tid] : make_float4(0.f, 0.f, 0.f, 0.f);
     RowRegs<NT> R;
-    fetch_rows<NT>(a.sv.rows, a.k, R);
+    fetch_rows<NT, DEFER>(a.sv.rows, a.k, R);
     const Record rec = a.sv.hdr->rec[(i + 1) & 1];
     if (rec.converged) return;
     if (tid < a.k) cen[tid] = pc;
-    store_rows<NT>(R, a.k, Ms);
+    store_rows<NT, DEFER>(R, a.k, Ms);
     for (int c = tid; c < a.k * NACC; c += NT) acc[c] = 0ull;
     if (tid == 0) dq.n = 0u;
     __syncthreads();

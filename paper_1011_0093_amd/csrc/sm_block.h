@@ -26,6 +26,7 @@ constexpr int kPass = kSearchThreads * kCpt;     // points per pass (4096)
 constexpr int kRowStride = kMaxK;                // bytes per row of M in device memory
 constexpr int kScanBatch = 8;                    // row entries fetched per scan step
 constexpr int kLaneCap = 32;                     // entries a lane scans before deferring
+constexpr int kRowPrefix = kLaneCap;             // row entries in LDS when scans defer
 constexpr int kDeferCap = 512;                   // deferred scans per block
 constexpr int kDeferMinK = 128;                  // smallest K whose search defers
 constexpr int kFusedMaxK = 32;                   // largest K sorted inside the search block
@@ -110,12 +111,25 @@ struct RowRegs {
     uint4 v[kRegs];
 };
 
-template <int NT>
+// LDS row stride: PREFIX rows hold the first kRowPrefix entries only, other
+// rows all K - 1.
+template <bool PREFIX>
+__device__ __forceinline__ int lds_rows_stride(int K) {
+    return PREFIX ? kRowPrefix : lds_row_stride(K);
+}
+
+// 16-byte pieces per thread that fetch_rows / store_rows move
+template <int NT, bool PREFIX>
+constexpr int row_regs() {
+    return PREFIX ? (kMaxK * kRowPrefix / 16 + NT - 1) / NT : RowRegs<NT>::kRegs;
+}
+
+template <int NT, bool PREFIX = false>
 __device__ __forceinline__ void fetch_rows(const uint8_t *__restrict__ M, int K, RowRegs<NT> &R) {
-    const int per_row = lds_row_stride(K) / 16;
+    const int per_row = lds_rows_stride<PREFIX>(K) / 16;
     const int nq = K * per_row;
 #pragma unroll
-    for (int u = 0; u < RowRegs<NT>::kRegs; ++u) {
+    for (int u = 0; u < row_regs<NT, PREFIX>(); ++u) {
         const int q = threadIdx.x + u * NT;
         R.v[u] = make_uint4(0u, 0u, 0u, 0u);
         if (q < nq) {
@@ -125,13 +139,13 @@ __device__ __forceinline__ void fetch_rows(const uint8_t *__restrict__ M, int K,
     }
 }
 
-template <int NT>
+template <int NT, bool PREFIX = false>
 __device__ __forceinline__ void store_rows(const RowRegs<NT> &R, int K, uint8_t *Ms) {
-    const int rs = lds_row_stride(K);
+    const int rs = lds_rows_stride<PREFIX>(K);
     const int per_row = rs / 16;
     const int nq = K * per_row;
 #pragma unroll
-    for (int u = 0; u < RowRegs<NT>::kRegs; ++u) {
+    for (int u = 0; u < row_regs<NT, PREFIX>(); ++u) {
         const int q = threadIdx.x + u * NT;
         if (q < nq) {
             const int r = q / per_row, c = q - r * per_row;
@@ -147,27 +161,36 @@ __device__ __forceinline__ void load_rows(const uint8_t *__restrict__ M, int K, 
     store_rows<NT>(R, K, Ms);
 }
 
+// Where a scan reads row p: the LDS copy (stride rs) holds its first `len`
+// entries; entries from `len` on are read from device memory (g, the row of
+// M in the state).
+struct RowView {
+    const uint8_t *lds;
+    const uint8_t *g;
+    int len;
+};
+
 // Sort-means scan (Alg. 2, inner loop) of point x from its previous center
 // p over the LDS copy of M: starting from d(x, c_p), centers are taken in row
 // order until the first t with d(c_p, c_t)^2 >= thr = 4 (1 + 2^-16) d(x, c_p)^2.
 //
 // sm_scan_range takes the row entries [j, min(j_end, K - 1)) in batches of
-// kScanBatch (one 8-byte LDS read of the row, the center reads issued
-// together, then the entries taken in order; distances computed past the
-// stop are discarded) and returns whether the scan has ended (stop found or
-// row exhausted); j is left at the next batch.  Reads past the row's K - 1
-// entries stay inside the LDS row (its stride is a multiple of 16) and the
+// kScanBatch (one 8-byte read of the row, the center reads issued together,
+// then the entries taken in order; distances computed past the stop are
+// discarded) and returns whether the scan has ended (stop found or row
+// exhausted); j is left at the next batch.  Reads past the row's K - 1
+// entries stay inside the row (its strides are multiples of 16) and the
 // center table.
 __device__ __forceinline__ bool sm_scan_range(float x, float y, float z, int p, int K,
-                                              const float4 *cen, const uint8_t *Ms, int rs,
-                                              float thr, int &j, int j_end, float &bd, int &best,
+                                              const float4 *cen, const RowView &row, float thr,
+                                              int &j, int j_end, float &bd, int &best,
                                               uint32_t &ev) {
     const float4 cp = cen[p];
-    const uint8_t *row = Ms + p * rs;
     const int n = K - 1;
     const int jm = j_end < n ? j_end : n;
     for (; j < jm; j += kScanBatch) {
-        const uint2 w8 = *(const uint2 *)(row + j);
+        const uint2 w8 = j + kScanBatch <= row.len ? *(const uint2 *)(row.lds + j)
+                                                   : *(const uint2 *)(row.g + j);
         float dpt[kScanBatch], d[kScanBatch];
         int t[kScanBatch];
 #pragma unroll
@@ -266,19 +289,17 @@ __device__ __forceinline__ unsigned long long scan_key(float d, int t, int p) {
 // argument is the same in all lanes, and all 64 lanes must call it; the
 // results (bd, best, evaluations made) are the same in all lanes.
 __device__ __forceinline__ void sm_finish_wave(float x, float y, float z, int p, int K,
-                                               const float4 *cen, const uint8_t *Ms, int rs,
-                                               float thr, int j, float &bd, int &best,
-                                               uint32_t &evals) {
+                                               const float4 *cen, const RowView &row, float thr,
+                                               int j, float &bd, int &best, uint32_t &evals) {
     const int lane = threadIdx.x & 63;
     const int n = K - 1;
     const float4 cp = cen[p];
-    const uint8_t *row = Ms + p * rs;
     unsigned long long bk = scan_key(bd, best, p);
     uint32_t sev = 0;
     for (int jb = j; jb < n; jb += 64) {
         const int jj = jb + lane;
         const bool in = jj < n;
-        const int t = in ? row[jj] : 0;
+        const int t = !in ? 0 : jj < row.len ? row.lds[jj] : row.g[jj];
         const float4 ct = cen[t];
         const float dpt = sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z);
         const float d = sq_dist(x, y, z, ct.x, ct.y, ct.z);
