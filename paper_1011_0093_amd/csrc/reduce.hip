@@ -10,9 +10,11 @@
 //              grouped by slice (a tile-local counting sort), 2 bytes per
 //              pixel with 16-byte stores, together with an (offset, count)
 //              word per (slice, tile).
-//   compact    one block per slice.  Sixteen lanes read one tile's segment
-//              of the slice together with 16-byte loads, several segments'
-//              loads in flight at once, into a 2^15-bin LDS histogram; the non-empty bins are compacted in
+//   compact    one block per slice.  The slice's (offset, count) words are
+//              loaded first; then sixteen lanes read one tile's segment of
+//              the slice together with 16-byte loads, several segments'
+//              loads in flight at once, into a 2^15-bin LDS histogram; the
+//              non-empty bins are compacted in
 //              ascending order, and the slice's place in the output comes
 //              from a decoupled look-back over the slices before it, 64
 //              predecessors per step.
@@ -27,7 +29,8 @@ constexpr int kPartThreads = 1024;
 constexpr int kMaxPpt = 16;                       // pixels per thread (max)
 constexpr int kMaxTile = kPartThreads * kMaxPpt;  // 16384 pixels
 constexpr int kCompactThreads = 1024;
-constexpr int kGroupsInFlight = 4;                // 16-byte loads in flight per lane
+constexpr int kSegsInFlight = 8;                  // 16-byte loads in flight per lane
+static_assert(16 % kSegsInFlight == 0, "a step never passes the 16th group of a chunk");
 constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagPrefix = 2ull << 62;
 constexpr unsigned long long kValueMask = (1ull << 62) - 1;
@@ -175,42 +178,55 @@ __global__ __launch_bounds__(kCompactThreads) void reduce_compact_kernel(
     __syncthreads();
 
     // Segments are read 16 lanes to a segment (256 contiguous bytes per
-    // quarter-wave and step), four tiles per wave instruction, and
-    // kGroupsInFlight groups of four tiles with their loads in flight together.
+    // quarter-wave and step), four tiles per wave instruction.  The slice's
+    // (offset, count) words are loaded first, 1024 tiles at a time: in group
+    // i (tiles 64 i .. 64 i + 63 of the chunk) wave w takes tiles 64 i + 4 w
+    // + q, quarter q = 0..3, so that every wave has work however few tiles
+    // there are; lane 4 i + q of the wave holds that tile's word.  The loads
+    // of kSegsInFlight segments are in flight together.
     {
         const int q = lane >> 4, ql = lane & 15;
-        const int64_t ngroups = (ntiles + 3) / 4;
-        for (int64_t G0 = wave; G0 < ngroups; G0 += (kCompactThreads / 64) * kGroupsInFlight) {
-            size_t s0[kGroupsInFlight], s1[kGroupsInFlight];
+        for (int64_t c0 = 0; c0 < ntiles; c0 += kCompactThreads) {
+            const int64_t tw = c0 + 64 * (lane >> 2) + 4 * wave + (lane & 3);
+            const uint32_t w = tw < ntiles ? info[(size_t)s * ntiles + tw] : 0u;
+            const int64_t left = ntiles - c0;
+            const int groups = left >= kCompactThreads ? 16 : (int)((left + 63) / 64);
+            // segment bounds are relative to the chunk's first key (at most
+            // 1024 tiles of 16384 keys: they fit 32 bits)
+            const uint16_t *kb = keys16 + (size_t)c0 * tile;
+            for (int i0 = 0; i0 < groups; i0 += kSegsInFlight) {
+                uint32_t s0[kSegsInFlight], s1[kSegsInFlight];
 #pragma unroll
-            for (int u = 0; u < kGroupsInFlight; ++u) {
-                const int64_t G = G0 + (int64_t)(kCompactThreads / 64) * u;
-                const int64_t g = G * 4 + q;
-                const uint32_t w = (G < ngroups && g < ntiles) ? info[(size_t)s * ntiles + g] : 0u;
-                s0[u] = (size_t)(g < ntiles ? g : 0) * tile + (w >> 16);
-                s1[u] = s0[u] + (w & 0xFFFFu);
-            }
-            for (size_t win = 0;; win += 128) {
-                bool any = false;
-#pragma unroll
-                for (int u = 0; u < kGroupsInFlight; ++u)
-                    any = any || ((s0[u] & ~(size_t)7) + win < s1[u]);
-                if (__ballot(any) == 0ull) break;  // wave-uniform exit
-                uint4 v[kGroupsInFlight];
-                size_t a[kGroupsInFlight];
-#pragma unroll
-                for (int u = 0; u < kGroupsInFlight; ++u) {
-                    a[u] = (s0[u] & ~(size_t)7) + win + 8 * ql;
-                    v[u] = a[u] < s1[u] ? *(const uint4 *)(keys16 + a[u]) : make_uint4(0, 0, 0, 0);
+                for (int u = 0; u < kSegsInFlight; ++u) {
+                    const int i = i0 + u;
+                    const uint32_t wu = (uint32_t)__shfl((int)w, 4 * i + q, 64);  // 0 past the end
+                    const uint32_t t = (uint32_t)(64 * i + 4 * wave + q);
+                    s0[u] = t * (uint32_t)tile + (wu >> 16);
+                    s1[u] = s0[u] + (wu & 0xFFFFu);
                 }
+                for (uint32_t win = 0;; win += 128) {
+                    bool any = false;
 #pragma unroll
-                for (int u = 0; u < kGroupsInFlight; ++u) {
-                    const uint32_t wd[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+                    for (int u = 0; u < kSegsInFlight; ++u)
+                        any = any || ((s0[u] & ~7u) + win < s1[u]);
+                    if (__ballot(any) == 0ull) break;  // wave-uniform exit
+                    uint4 v[kSegsInFlight];
+                    uint32_t a[kSegsInFlight];
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const size_t pos = a[u] + e;
-                        if (pos >= s0[u] && pos < s1[u])
-                            atomicAdd(&hist[(wd[e >> 1] >> (16 * (e & 1))) & 0xFFFFu], 1u);
+                    for (int u = 0; u < kSegsInFlight; ++u) {
+                        a[u] = (s0[u] & ~7u) + win + 8 * ql;
+                        v[u] = a[u] < s1[u] ? *(const uint4 *)(kb + a[u]) : make_uint4(0, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < kSegsInFlight; ++u) {
+                        if (i0 + u >= groups) break;  // block-uniform: no tiles left
+                        const uint32_t wd[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const uint32_t pos = a[u] + e;
+                            if (pos >= s0[u] && pos < s1[u])
+                                atomicAdd(&hist[(wd[e >> 1] >> (16 * (e & 1))) & 0xFFFFu], 1u);
+                        }
                     }
                 }
             }

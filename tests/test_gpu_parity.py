@@ -97,6 +97,20 @@ def test_reduce_unaligned_input_and_full_size():
     assert np.array_equal(_u32(col), rc) and np.array_equal(_u32(cnt), rn)
 
 
+def test_reduce_more_tiles_than_one_chunk():
+    # 4196 x 4096 pixels = 1050 tiles of 16384: the compaction reads the
+    # slice words in chunks of 1024 tiles, and the second chunk ends inside
+    # its first group of 64 tiles.
+    wsm = _wsm()
+    big = synth.workload_image("large", 0)
+    img = np.concatenate([big, big[:100, ::-1]], axis=0)
+    _say("reduce", img.shape, "1050 tiles")
+    col, cnt = wsm.reduce_colors(_gpu_img(img))
+    rc, rn = oracle.reduce_colors(img)
+    assert np.array_equal(_u32(col), rc) and np.array_equal(_u32(cnt), rn)
+    assert int(rn.sum()) == img.shape[0] * img.shape[1]
+
+
 # ---------------------------------------------------------------------------
 # Iterations, lock-step: one GPU iteration at a time, the oracle redoes each
 # step from the GPU's own float32 centers and memberships.
