@@ -330,7 +330,8 @@ template <bool PACKED, bool FULL, bool DEFER>
 __device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const uint8_t *Ms,
                              unsigned long long *acc, double *dscr, unsigned long long *uscr,
                              DeferQueue *dq, uint32_t (&key)[kCpt], uint32_t (&cnt)[kCpt],
-                             int (&pm)[kCpt], bool first = false) {
+                             int (&pm)[kCpt], bool first = false, const float *Dd = nullptr,
+                             FlatScratch *fs = nullptr) {
     constexpr int NT = kSearchThreads;
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x;
@@ -375,23 +376,28 @@ __device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const 
                 }
             } else if (!DEFER) {
                 if (valid) best = sm_scan(x, y, z, pm[r], a.k, cen, Ms, rs, bd, ev);
-            } else if (valid) {
-                const float thr = sm_scan_begin(x, y, z, pm[r], cen, bd, best, ev);
-                const RowView rv{Ms + pm[r] * rs, a.sv.rows + (size_t)pm[r] * kRowStride,
-                                 kRowPrefix};
-                int j = 0, j_end = kLaneCap;
-                for (;;) {
-                    done = sm_scan_range(x, y, z, pm[r], a.k, cen, rv, thr, j, j_end, bd, best,
-                                         ev);
-                    if (done) break;
+            } else {
+                // the wave's scans over the row heads together; a scan that
+                // goes past the head is deferred (or, with the queue full,
+                // carried on by its lane)
+                float thr;
+                bool more;
+                sm_scan_flat(valid, key[r], pm[r], a.k, cen, Ms, Dd, fs[wave], thr, bd, best, ev,
+                             more);
+                if (more) {
                     const uint32_t q = atomicAdd(&dq->n, 1u);
                     if (q < (uint32_t)kDeferCap) {
                         dq->idx[q] = (uint32_t)idx;
                         dq->bd[q] = __float_as_uint(bd);
-                        dq->pjb[q] = ((uint32_t)j << 16) | ((uint32_t)pm[r] << 8) | (uint32_t)best;
-                        break;
+                        dq->pjb[q] = ((uint32_t)kRowPrefix << 16) | ((uint32_t)pm[r] << 8) |
+                                     (uint32_t)best;
+                        done = false;
+                    } else {
+                        const RowView rv{Ms + pm[r] * rs, a.sv.rows + (size_t)pm[r] * kRowStride,
+                                         kRowPrefix};
+                        int j = kRowPrefix;
+                        sm_scan_range(x, y, z, pm[r], a.k, cen, rv, thr, j, a.k, bd, best, ev);
                     }
-                    j_end = a.k;  // queue full: carry on in place
                 }
             }
             if (valid && done) {
@@ -421,7 +427,8 @@ __global__ __launch_bounds__(kSortThreads) void rows_kernel(IterArgs a, int i) {
         unsigned long long *T = a.sv.totals + (size_t)(i % 3) * kMaxK * 4;
         for (int c = threadIdx.x; c < kMaxK * 4; c += kSortThreads) T[c] = 0ull;
     }
-    sort_row<kSortThreads>(cen, a.k, p, keys, rank, a.sv.rows + (size_t)p * kRowStride);
+    sort_row<kSortThreads>(cen, a.k, p, keys, rank, a.sv.rows + (size_t)p * kRowStride,
+                           a.sv.rowd + (size_t)p * kRowDist);
 }
 
 // Sort-means step i, second launch: every block copies the centers and M
@@ -432,6 +439,9 @@ __global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int 
     __shared__ unsigned long long acc[kMaxK * 4];
     // rows of M: the first kRowPrefix entries when scans defer, else whole
     __shared__ __align__(16) uint8_t Ms[kMaxK * (DEFER ? kRowPrefix : kRowStride)];
+    // with DEFER: the distances of those entries, and the flat scans' scratch
+    __shared__ __align__(16) float Dd[DEFER ? kMaxK * kRowDist : 4];
+    __shared__ FlatScratch fs[DEFER ? kSearchThreads / 64 : 1];
     __shared__ DeferQueue dq;
     __shared__ double dscr[kSearchThreads / 64];
     __shared__ unsigned long long uscr[kSearchThreads / 64];
@@ -447,17 +457,36 @@ __global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int 
     const float4 pc = tid < a.k ? pal[tid] : make_float4(0.f, 0.f, 0.f, 0.f);
     RowRegs<NT> R;
     fetch_rows<NT, DEFER>(a.sv.rows, a.k, R);
+    constexpr int kDdRegs = DEFER ? kMaxK * kRowDist / 4 / NT : 1;  // 16-byte pieces per thread
+    static_assert(!DEFER || kMaxK * kRowDist / 4 == kDdRegs * NT, "distance copy");
+    uint4 dreg[kDdRegs];
+    if (DEFER) {
+#pragma unroll
+        for (int u = 0; u < kDdRegs; ++u) {
+            const int q = tid + u * NT;
+            dreg[u] = q < a.k * (kRowDist / 4) ? ((const uint4 *)a.sv.rowd)[q]
+                                               : make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
     const Record rec = a.sv.hdr->rec[(i + 1) & 1];
     if (rec.converged) return;
     if (tid < a.k) cen[tid] = pc;
     store_rows<NT, DEFER>(R, a.k, Ms);
+    if (DEFER) {
+#pragma unroll
+        for (int u = 0; u < kDdRegs; ++u) {
+            const int q = tid + u * NT;
+            if (q < a.k * (kRowDist / 4)) ((uint4 *)Dd)[q] = dreg[u];
+        }
+    }
     for (int c = tid; c < a.k * NACC; c += NT) acc[c] = 0ull;
     if (tid == 0) dq.n = 0u;
     __syncthreads();
     // The launch for a call's first step (FIRST) checks whether the state has
     // completed no step yet, i.e. every membership is still 0 (state init).
     const bool first = FIRST && rec.iters == 0;
-    search_chunk<PACKED, false, DEFER>(a, i, cen, Ms, acc, dscr, uscr, &dq, key, cnt, pm, first);
+    search_chunk<PACKED, false, DEFER>(a, i, cen, Ms, acc, dscr, uscr, &dq, key, cnt, pm, first,
+                                       Dd, fs);
 }
 
 // Rows of M for palette slot 0 of the state (the pixel map's palette).
@@ -466,7 +495,8 @@ __global__ __launch_bounds__(kSortThreads) void palette_rows_kernel(StateView sv
     __shared__ __align__(16) unsigned long long keys[kMaxK];
     __shared__ uint32_t rank[kMaxK];
     for (int c = threadIdx.x; c < K; c += kSortThreads) cen[c] = sv.pal[c];
-    sort_row<kSortThreads>(cen, K, blockIdx.x, keys, rank, sv.rows + (size_t)blockIdx.x * kRowStride);
+    sort_row<kSortThreads>(cen, K, blockIdx.x, keys, rank, sv.rows + (size_t)blockIdx.x * kRowStride,
+                           nullptr);
 }
 
 // Sort-means step for K <= kFusedMaxK in one launch: every block applies

@@ -27,6 +27,7 @@ constexpr int kRowStride = kMaxK;                // bytes per row of M in device
 constexpr int kScanBatch = 8;                    // row entries fetched per scan step
 constexpr int kLaneCap = 32;                     // entries a lane scans before deferring
 constexpr int kRowPrefix = kLaneCap;             // row entries in LDS when scans defer
+static_assert(kRowPrefix == kRowDist, "the stored distances cover the LDS row prefix");
 constexpr int kDeferCap = 512;                   // deferred scans per block
 constexpr int kDeferMinK = 128;                  // smallest K whose search defers
 constexpr int kFusedMaxK = 32;                   // largest K sorted inside the search block
@@ -54,11 +55,12 @@ __device__ __forceinline__ bool run_tail(int key, bool valid) {
 // key of center t is (distance bits, t): distances are non-negative, so
 // their bit patterns order like the values, and the keys are distinct.  The
 // rank of each key is counted by NT / kMaxK threads over slices of the
-// others.  All NT threads call it; it starts with a barrier, so consecutive
-// calls may reuse the scratch.
+// others.  If drow is not null, the distances of the first kRowDist entries
+// are written to it as well.  All NT threads call it; it starts with a
+// barrier, so consecutive calls may reuse the scratch.
 template <int NT>
 __device__ void sort_row(const float4 *cen, int K, int p, unsigned long long *__restrict__ keys,
-                         uint32_t *rank, uint8_t *__restrict__ row) {
+                         uint32_t *rank, uint8_t *__restrict__ row, float *__restrict__ drow) {
     static_assert(NT % kMaxK == 0, "block size");
     constexpr int Q = NT / kMaxK;
     constexpr int span = kMaxK / Q;
@@ -97,8 +99,13 @@ __device__ void sort_row(const float4 *cen, int K, int p, unsigned long long *__
             atomicAdd(&rank[t], r);
     }
     __syncthreads();
-    for (int c = tid; c < K; c += NT)
-        if (c != p) row[rank[c]] = (uint8_t)c;
+    for (int c = tid; c < K; c += NT) {
+        if (c != p) {
+            const uint32_t rk = rank[c];
+            row[rk] = (uint8_t)c;
+            if (drow && rk < (uint32_t)kRowDist) drow[rk] = __uint_as_float((uint32_t)(keys[c] >> 32));
+        }
+    }
 }
 
 // Copy the K rows of M (device layout, kRowStride bytes per row) into LDS
@@ -314,6 +321,88 @@ __device__ __forceinline__ void sm_finish_wave(float x, float y, float z, int p,
     bd = __uint_as_float((uint32_t)(bk >> 32));
     best = (bk & 0x100ull) ? (int)(bk & 0xFFull) : p;
     evals = sev;
+}
+
+// LDS scratch of one wave for sm_scan_flat.
+struct FlatScratch {
+    unsigned long long kp[64];  // lane l: color key | (previous center << 16 | first pair) << 32
+    unsigned long long bk[64];  // lane l: smallest scan_key so far
+    __align__(16) uint8_t head[64 * kRowPrefix];  // pair q: 1 + the lane whose pairs start at q
+};
+
+// Sort-means scans of a wave's points (lane l: the point with color `key` and
+// previous center p, if valid) over the first L = min(K - 1, kRowPrefix)
+// entries of their rows, with the entries spread evenly over the lanes
+// rather than each lane scanning its own row: scan lengths differ a lot
+// within a wave, and a wave runs as long as its longest lane.
+//   Row p is ascending in d(c_p, c_t)^2, so the entries before the break are
+// the first n, n = the number of stored distances Dd[p][.] below the
+// threshold (a binary search).  The wave lists its (point, entry) pairs in
+// lane order; lane l takes pairs l, l + 64, ..., finds the pair's point from
+// the marks of where each point's pairs start (a running maximum over the
+// wave), and folds the pair's scan_key into that point's LDS minimum.
+//   The result is the sequential scan's: bd, best, evaluations 1 + n, and
+// `more` when the break lies past entry L - 1 and the row goes on (the scan
+// then continues from entry L with threshold thr).  Ms holds rows of
+// kRowPrefix entries.  All 64 lanes call it.  Lanes of one wave exchange
+// data through LDS here; LDS operations of a wave take effect in issue
+// order, and signal fences keep the compiler from reordering them.
+__device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, int K,
+                                             const float4 *cen, const uint8_t *Ms,
+                                             const float *Dd, FlatScratch &fs, float &thr,
+                                             float &bd, int &best, uint32_t &ev, bool &more) {
+    const int lane = threadIdx.x & 63;
+    const int L = K - 1 < kRowPrefix ? K - 1 : kRowPrefix;
+    const int pp = valid ? p : 0;
+    float x, y, z;
+    unpack_key(key, x, y, z);
+    const float4 cp = cen[pp];
+    const float prev = sq_dist(x, y, z, cp.x, cp.y, cp.z);
+    thr = prev * kBreakScale;
+    const float *dr = Dd + pp * kRowPrefix;
+    int n = 0;
+#pragma unroll
+    for (int step = kRowPrefix; step > 0; step >>= 1)
+        if (n + step <= L && dr[n + step - 1] < thr) n += step;
+    if (!valid) n = 0;
+    more = valid && n == L && L < K - 1;
+    const uint32_t incl = wave_incl_sum((uint32_t)n);
+    const int excl = (int)incl - n;
+    const int total = (int)wave_last_u32(incl);
+    uint4 *h4 = (uint4 *)fs.head;
+    static_assert(sizeof(fs.head) == 64 * 2 * 16, "two 16-byte stores per lane clear the marks");
+    h4[lane] = make_uint4(0u, 0u, 0u, 0u);
+    h4[lane + 64] = make_uint4(0u, 0u, 0u, 0u);
+    fs.kp[lane] = (unsigned long long)key |
+                  ((unsigned long long)(((uint32_t)pp << 16) | (uint32_t)excl) << 32);
+    fs.bk[lane] = scan_key(prev, pp, pp);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (n > 0) fs.head[excl] = (uint8_t)(lane + 1);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    uint32_t carry = 0u;
+    for (int q0 = 0; q0 < total; q0 += 64) {  // wave-uniform
+        const int q = q0 + lane;
+        const bool act = q < total;
+        uint32_t o1 = wave_seg_max(0, act ? (uint32_t)fs.head[q] : 0u);
+        o1 = o1 > carry ? o1 : carry;
+        carry = wave_last_u32(o1);
+        if (act) {
+            const int o = (int)o1 - 1;
+            const unsigned long long kp = fs.kp[o];
+            const uint32_t pe = (uint32_t)(kp >> 32);
+            const int po = (int)(pe >> 16);
+            const int t = Ms[po * kRowPrefix + (q - (int)(pe & 0xFFFFu))];
+            const float4 ct = cen[t];
+            float xo, yo, zo;
+            unpack_key((uint32_t)kp, xo, yo, zo);
+            atomicMin(&fs.bk[o], scan_key(sq_dist(xo, yo, zo, ct.x, ct.y, ct.z), t, po));
+        }
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    const unsigned long long b = fs.bk[lane];
+    bd = __uint_as_float((uint32_t)(b >> 32));
+    best = (b & 0x100ull) ? (int)(b & 0xFFull) : pp;
+    if (valid) ev += 1u + (uint32_t)n;
 }
 
 // The number of evaluations the sort-means scan of x from p makes: 1 (the

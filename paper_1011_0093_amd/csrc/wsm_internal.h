@@ -78,7 +78,9 @@ constexpr size_t kOffSseHist = kOffEvalPart + 2 * kMaxGrid * 8;       // double[
 constexpr size_t kOffEvalHist = kOffSseHist + kHistory * 8;           // int64[kHistory]
 constexpr size_t kOffMapPart = kOffEvalHist + kHistory * 8;           // double[kMaxGrid]
 constexpr size_t kOffRows = align_up(kOffMapPart + kMaxGrid * 8, 256);  // u8[256][256]
-constexpr size_t kOffMembership = kOffRows + (size_t)kMaxK * kMaxK;
+constexpr int kRowDist = 32;  // leading entries of each row whose distances are kept
+constexpr size_t kOffRowDist = kOffRows + (size_t)kMaxK * kMaxK;  // float[256][kRowDist]
+constexpr size_t kOffMembership = kOffRowDist + (size_t)kMaxK * kRowDist * 4;
 
 inline size_t state_bytes_for(int64_t n_points) {
     return kOffMembership + align_up((size_t)n_points, 256);
@@ -95,6 +97,7 @@ struct StateView {
     long long *eval_hist;
     double *map_part;     // [kMaxGrid]
     uint8_t *rows;        // [256][256]: sorted neighbour rows (M without self)
+    float *rowd;          // [256][kRowDist]: d(c_p, c_t)^2 of the first entries of row p
     uint8_t *m;           // [n_points]
 };
 
@@ -110,6 +113,7 @@ inline StateView make_view(void *state) {
     v.eval_hist = (long long *)(b + kOffEvalHist);
     v.map_part = (double *)(b + kOffMapPart);
     v.rows = (uint8_t *)(b + kOffRows);
+    v.rowd = (float *)(b + kOffRowDist);
     v.m = (uint8_t *)(b + kOffMembership);
     return v;
 }
