@@ -249,6 +249,8 @@ __device__ __forceinline__ void prefetch_points(const IterArgs &a, uint32_t (&ke
 struct DeferQueue {
     uint32_t n;
     uint32_t idx[kDeferCap];    // point index
+    uint32_t key[kDeferCap];    // its color and count
+    uint32_t cnt[kDeferCap];
     uint32_t bd[kDeferCap];     // best distance so far (float bits)
     uint32_t pjb[kDeferCap];    // next entry << 16 | previous center << 8 | best center
 };
@@ -268,40 +270,59 @@ __device__ void finish_block(const IterArgs &a, int i, const float4 *cen, const 
     const int wave = tid >> 6;
     const int rs = lds_rows_stride<DEFER>(a.k);
     if (DEFER) {
-        // The deferred scans: wave w takes queue entries w, w + NW, ...
+        // The deferred scans: wave w takes queue entries w, w + NW, ...; the
+        // row entries of the first step of kDeferBatch of them are loaded
+        // together (the rows past their LDS heads are in device memory).
         __syncthreads();
         const uint32_t nd = dq->n < (uint32_t)kDeferCap ? dq->n : (uint32_t)kDeferCap;
-        for (uint32_t q = wave; q < nd; q += NW) {
-            const uint32_t idx = dq->idx[q], pjb = dq->pjb[q];
-            const int p = (int)((pjb >> 8) & 0xFFu);
-            int best = (int)(pjb & 0xFFu);
-            float bd = __uint_as_float(dq->bd[q]);
-            uint32_t k, c;
-            load_point(a.pts, idx, k, c);
-            float x, y, z;
-            unpack_key(k, x, y, z);
-            const float4 cp = cen[p];
-            const float thr = sq_dist(x, y, z, cp.x, cp.y, cp.z) * kBreakScale;
-            uint32_t sev = 0;
-            const RowView rv{Ms + p * rs, a.sv.rows + (size_t)p * kRowStride, kRowPrefix};
-            sm_finish_wave(x, y, z, p, a.k, cen, rv, thr, (int)(pjb >> 16), bd, best, sev);
-            // one lane records the result (stores and LDS atomics only)
-            const bool me = lane == 0;
-            ev += me ? sev : 0u;
-            sse += me ? (double)c * (double)bd : 0.0;
-            if (me) {
-                a.sv.m[idx] = (uint8_t)best;
-                const unsigned long long cc = c;
-                const unsigned long long rr = (k >> 16) & 0xFFu, gg = (k >> 8) & 0xFFu,
-                                         bb = k & 0xFFu;
-                if (PACKED) {
-                    atomicAdd(&acc[best * 2 + 0], cc * rr | ((cc * gg) << 32));
-                    atomicAdd(&acc[best * 2 + 1], cc * bb | (cc << 32));
-                } else {
-                    atomicAdd(&acc[best * 4 + 0], cc * rr);
-                    atomicAdd(&acc[best * 4 + 1], cc * gg);
-                    atomicAdd(&acc[best * 4 + 2], cc * bb);
-                    atomicAdd(&acc[best * 4 + 3], cc);
+        for (uint32_t q0 = wave; q0 < nd; q0 += NW * kDeferBatch) {
+            int tf[kDeferBatch];
+#pragma unroll
+            for (int u = 0; u < kDeferBatch; ++u) {
+                const uint32_t q = q0 + (uint32_t)(u * NW);
+                tf[u] = 0;
+                if (q < nd) {
+                    const uint32_t pjb = dq->pjb[q];
+                    const int jj = (int)(pjb >> 16) + lane;
+                    const size_t row = (size_t)((pjb >> 8) & 0xFFu) * kRowStride;
+                    if (jj < a.k - 1) tf[u] = a.sv.rows[row + jj];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kDeferBatch; ++u) {
+                const uint32_t q = q0 + (uint32_t)(u * NW);
+                if (q >= nd) break;  // wave-uniform
+                const uint32_t idx = dq->idx[q], pjb = dq->pjb[q];
+                const int p = (int)((pjb >> 8) & 0xFFu);
+                int best = (int)(pjb & 0xFFu);
+                float bd = __uint_as_float(dq->bd[q]);
+                const uint32_t k = dq->key[q], c = dq->cnt[q];
+                float x, y, z;
+                unpack_key(k, x, y, z);
+                const float4 cp = cen[p];
+                const float thr = sq_dist(x, y, z, cp.x, cp.y, cp.z) * kBreakScale;
+                uint32_t sev = 0;
+                const RowView rv{Ms + p * rs, a.sv.rows + (size_t)p * kRowStride, kRowPrefix};
+                sm_finish_wave(x, y, z, p, a.k, cen, rv, thr, (int)(pjb >> 16), tf[u], bd, best,
+                               sev);
+                // one lane records the result (stores and LDS atomics only)
+                const bool me = lane == 0;
+                ev += me ? sev : 0u;
+                sse += me ? (double)c * (double)bd : 0.0;
+                if (me) {
+                    a.sv.m[idx] = (uint8_t)best;
+                    const unsigned long long cc = c;
+                    const unsigned long long rr = (k >> 16) & 0xFFu, gg = (k >> 8) & 0xFFu,
+                                             bb = k & 0xFFu;
+                    if (PACKED) {
+                        atomicAdd(&acc[best * 2 + 0], cc * rr | ((cc * gg) << 32));
+                        atomicAdd(&acc[best * 2 + 1], cc * bb | (cc << 32));
+                    } else {
+                        atomicAdd(&acc[best * 4 + 0], cc * rr);
+                        atomicAdd(&acc[best * 4 + 1], cc * gg);
+                        atomicAdd(&acc[best * 4 + 2], cc * bb);
+                        atomicAdd(&acc[best * 4 + 3], cc);
+                    }
                 }
             }
         }
@@ -388,6 +409,8 @@ __device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const 
                     const uint32_t q = atomicAdd(&dq->n, 1u);
                     if (q < (uint32_t)kDeferCap) {
                         dq->idx[q] = (uint32_t)idx;
+                        dq->key[q] = key[r];
+                        dq->cnt[q] = cnt[r];
                         dq->bd[q] = __float_as_uint(bd);
                         dq->pjb[q] = ((uint32_t)kRowPrefix << 16) | ((uint32_t)pm[r] << 8) |
                                      (uint32_t)best;

@@ -29,6 +29,7 @@ constexpr int kLaneCap = 32;                     // entries a lane scans before 
 constexpr int kRowPrefix = kLaneCap;             // row entries in LDS when scans defer
 static_assert(kRowPrefix == kRowDist, "the stored distances cover the LDS row prefix");
 constexpr int kDeferCap = 512;                   // deferred scans per block
+constexpr int kDeferBatch = 8;                   // deferred scans a wave fetches rows for at once
 constexpr int kDeferMinK = 128;                  // smallest K whose search defers
 constexpr int kFusedMaxK = 32;                   // largest K sorted inside the search block
 
@@ -293,11 +294,14 @@ __device__ __forceinline__ unsigned long long scan_key(float d, int t, int p) {
 // The rest of one point's scan, from row entry j, by the whole wave: lane l
 // takes entry j + l, the stop is the first entry (in row order) at or past
 // the threshold, and the entries before it are reduced with scan_key.  Every
-// argument is the same in all lanes, and all 64 lanes must call it; the
-// results (bd, best, evaluations made) are the same in all lanes.
+// argument but t_first is the same in all lanes, and all 64 lanes must call
+// it; t_first is row entry j + lane, loaded by the caller (any value where
+// j + lane >= K - 1).  The results (bd, best, evaluations made) are the same
+// in all lanes.
 __device__ __forceinline__ void sm_finish_wave(float x, float y, float z, int p, int K,
                                                const float4 *cen, const RowView &row, float thr,
-                                               int j, float &bd, int &best, uint32_t &evals) {
+                                               int j, int t_first, float &bd, int &best,
+                                               uint32_t &evals) {
     const int lane = threadIdx.x & 63;
     const int n = K - 1;
     const float4 cp = cen[p];
@@ -306,7 +310,7 @@ __device__ __forceinline__ void sm_finish_wave(float x, float y, float z, int p,
     for (int jb = j; jb < n; jb += 64) {
         const int jj = jb + lane;
         const bool in = jj < n;
-        const int t = !in ? 0 : jj < row.len ? row.lds[jj] : row.g[jj];
+        const int t = !in ? 0 : jb == j ? t_first : jj < row.len ? row.lds[jj] : row.g[jj];
         const float4 ct = cen[t];
         const float dpt = sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z);
         const float d = sq_dist(x, y, z, ct.x, ct.y, ct.z);
@@ -325,8 +329,9 @@ __device__ __forceinline__ void sm_finish_wave(float x, float y, float z, int p,
 
 // LDS scratch of one wave for sm_scan_flat.
 struct FlatScratch {
-    unsigned long long kp[64];  // lane l: color key | (previous center << 16 | first pair) << 32
-    unsigned long long bk[64];  // lane l: smallest scan_key so far
+    float4 pt[64];               // lane l: the point (x, y, z) and, as int bits, the
+                                 // offset of its pair q's row entry: p * kRowPrefix - first pair
+    unsigned long long bk[64];   // lane l: smallest scan_key so far
     __align__(16) uint8_t head[64 * kRowPrefix];  // pair q: 1 + the lane whose pairs start at q
 };
 
@@ -340,7 +345,9 @@ struct FlatScratch {
 // threshold (a binary search).  The wave lists its (point, entry) pairs in
 // lane order; lane l takes pairs l, l + 64, ..., finds the pair's point from
 // the marks of where each point's pairs start (a running maximum over the
-// wave), and folds the pair's scan_key into that point's LDS minimum.
+// wave), and folds the pair's scan_key into that point's LDS minimum (a
+// row never lists its own center, so the pair's key is that of a center
+// other than the previous one).
 //   The result is the sequential scan's: bd, best, evaluations 1 + n, and
 // `more` when the break lies past entry L - 1 and the row goes on (the scan
 // then continues from entry L with threshold thr).  Ms holds rows of
@@ -373,8 +380,7 @@ __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, in
     static_assert(sizeof(fs.head) == 64 * 2 * 16, "two 16-byte stores per lane clear the marks");
     h4[lane] = make_uint4(0u, 0u, 0u, 0u);
     h4[lane + 64] = make_uint4(0u, 0u, 0u, 0u);
-    fs.kp[lane] = (unsigned long long)key |
-                  ((unsigned long long)(((uint32_t)pp << 16) | (uint32_t)excl) << 32);
+    fs.pt[lane] = make_float4(x, y, z, __int_as_float(pp * kRowPrefix - excl));
     fs.bk[lane] = scan_key(prev, pp, pp);
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if (n > 0) fs.head[excl] = (uint8_t)(lane + 1);
@@ -383,19 +389,15 @@ __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, in
     for (int q0 = 0; q0 < total; q0 += 64) {  // wave-uniform
         const int q = q0 + lane;
         const bool act = q < total;
-        uint32_t o1 = wave_seg_max(0, act ? (uint32_t)fs.head[q] : 0u);
+        uint32_t o1 = wave_incl_max(act ? (uint32_t)fs.head[q] : 0u);
         o1 = o1 > carry ? o1 : carry;
         carry = wave_last_u32(o1);
         if (act) {
             const int o = (int)o1 - 1;
-            const unsigned long long kp = fs.kp[o];
-            const uint32_t pe = (uint32_t)(kp >> 32);
-            const int po = (int)(pe >> 16);
-            const int t = Ms[po * kRowPrefix + (q - (int)(pe & 0xFFFFu))];
+            const float4 po = fs.pt[o];
+            const int t = Ms[__float_as_int(po.w) + q];
             const float4 ct = cen[t];
-            float xo, yo, zo;
-            unpack_key((uint32_t)kp, xo, yo, zo);
-            atomicMin(&fs.bk[o], scan_key(sq_dist(xo, yo, zo, ct.x, ct.y, ct.z), t, po));
+            atomicMin(&fs.bk[o], scan_key(sq_dist(po.x, po.y, po.z, ct.x, ct.y, ct.z), t, -1));
         }
     }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);

@@ -128,6 +128,25 @@ __device__ __forceinline__ uint32_t wave_seg_max(int head, uint32_t v) {
     return v;
 }
 
+// Inclusive maximum over the wave, in lane order.
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+    uint32_t t;
+    t = dpp_u32<kDppRowShr1>(v);
+    if (dpp_takes<kDppRowShr1>(lane)) v = v > t ? v : t;
+    t = dpp_u32<kDppRowShr2>(v);
+    if (dpp_takes<kDppRowShr2>(lane)) v = v > t ? v : t;
+    t = dpp_u32<kDppRowShr4>(v);
+    if (dpp_takes<kDppRowShr4>(lane)) v = v > t ? v : t;
+    t = dpp_u32<kDppRowShr8>(v);
+    if (dpp_takes<kDppRowShr8>(lane)) v = v > t ? v : t;
+    t = dpp_u32<kDppRowBcast15>(v);
+    if (dpp_takes<kDppRowBcast15>(lane)) v = v > t ? v : t;
+    t = dpp_u32<kDppRowBcast31>(v);
+    if (dpp_takes<kDppRowBcast31>(lane)) v = v > t ? v : t;
+    return v;
+}
+
 // Sum over the wave in a fixed order; the result is valid in lane 63.
 __device__ __forceinline__ double wave_sum_f64(double v) {
     const int lane = threadIdx.x & 63;
