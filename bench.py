@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/search_kernel_512x512_traffic.md).  It describes the kernel
 # sources it was measured on (hash below); for any other sources the bench
 # reports null.
-SEARCH_TRAFFIC_BYTES = 5627336
-SEARCH_TRAFFIC_SRC = "721041efa4e85382"
+SEARCH_TRAFFIC_BYTES = 3535241
+SEARCH_TRAFFIC_SRC = "cf4ea64661ac79c2"
 _KERNEL_SOURCES = ("iterate.hip", "sm_block.h", "wave_ops.h", "wsm_internal.h")
 
 
