@@ -11,7 +11,9 @@
 //   2. block p sorts row p of the neighbour matrix M for the new centers
 //      (Sec. 2: the inter-center distances with every row sorted).
 // Step i, search launch (one block per chunk of points):
-//   3. sort-means from each point's previous center over an LDS copy of M;
+//   3. sort-means from each point's previous center over an LDS copy of M
+//      (for K >= kDeferMinK a wave's scans over the row heads are spread
+//      over its lanes, and the rare longer ones finished by whole waves);
 //   4. sums count * (R, G, B, 1) per center: runs of equal centers within a
 //      wave are pre-summed with a segmented scan, then added into LDS, and
 //      each block flushes its non-zero sums with 64-bit device atomics (the
@@ -238,14 +240,13 @@ __device__ __forceinline__ void prefetch_points(const IterArgs &a, uint32_t (&ke
     }
 }
 
-// Deferred sort-means scans: lanes scan kLaneCap entries on their own; a
-// point whose scan is still open then goes to an LDS queue (while it has
-// room; otherwise the lane carries on) and is finished after the block's
-// passes by a whole wave (sm_finish_wave), so that the rare long scans do not
-// hold their wave for their full length.  The queue is kept short because in
-// the first iterations, when every point starts from center 0, most scans
-// are long.  The deferral costs registers, so it is compiled only into the
-// search kernel used for K >= kDeferMinK, where the long scans occur.
+// Deferred sort-means scans (search kernel for K >= kDeferMinK): a point
+// whose scan goes past the row head that sm_scan_flat covers goes to an LDS
+// queue (while it has room; otherwise its lane carries on alone) and is
+// finished after the block's passes by a whole wave (sm_finish_wave), so
+// that the rare long scans do not hold their wave.  The first step of a
+// call, when every point starts from center 0 and most scans are long,
+// runs its own kernel (the full search), so the queue can stay short.
 struct DeferQueue {
     uint32_t n;
     uint32_t idx[kDeferCap];    // point index

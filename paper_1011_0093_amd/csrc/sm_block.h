@@ -5,15 +5,19 @@
 // ascending (d(c_p, c_t)^2, t) order -- the row's first entry, p itself, is
 // left out, since the scan starts from the second one.  It is built once per
 // set of centers (sort_row, one block per row) and kept in device memory as
-// K rows of kRowStride bytes; a search block copies the K x (K - 1) bytes
-// into LDS.  (For K <= kFusedMaxK every search block sorts the rows itself.)
-// The scan recomputes d(c_p, c_t)^2 from the centers in LDS with the same
-// expression the rows were sorted by, so the break test sees bit-equal
-// values.
+// K rows of kRowStride bytes, with the distances of each row's first
+// kRowDist entries; a search block copies the rows (for K >= kDeferMinK only
+// their first kRowPrefix entries and those distances) into LDS.  (For K <=
+// kFusedMaxK every search block sorts the rows itself.)  A scan compares
+// d(c_p, c_t)^2 recomputed from the centers in LDS, or the stored value,
+// with the same expression the rows were sorted by, so the break test sees
+// bit-equal values.
 //
-// Scans are taken kScanBatch entries at a time.  For K >= kDeferMinK a lane
-// stops after kLaneCap entries and leaves the rest of a long scan to the
-// whole wave (sm_finish_wave), so that one long scan does not hold its wave.
+// For K < kDeferMinK a lane scans its own point's row, kScanBatch entries
+// at a time (sm_scan).  For K >= kDeferMinK a wave scans the row heads of
+// its 64 points together, with the entries dealt out evenly over the lanes
+// (sm_scan_flat), and the rare scans that go past the head are finished by
+// the whole wave (sm_finish_wave), so that no lane holds its wave.
 #pragma once
 
 #include "wave_ops.h"
