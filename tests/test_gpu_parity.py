@@ -169,7 +169,7 @@ def test_lockstep_small_k32(seed):
     print(stats[-1])
 
 
-@pytest.mark.parametrize("K", [16, 64, 256])
+@pytest.mark.parametrize("K", [16, 33, 47, 64, 256])
 def test_lockstep_medium(K):
     img = synth.workload_image("medium", 0)
     _say("lockstep medium seed 0 K", K)
