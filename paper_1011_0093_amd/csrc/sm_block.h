@@ -29,6 +29,7 @@ constexpr int kCpt = 4;                          // points per thread per pass
 constexpr int kPass = kSearchThreads * kCpt;     // points per pass (4096)
 constexpr int kRowStride = kMaxK;                // bytes per row of M in device memory
 constexpr int kScanBatch = 8;                    // row entries fetched per scan step
+static_assert(kMaxK % kScanBatch == 0, "a batched full scan stays inside the center table");
 constexpr int kLaneCap = 32;                     // entries a lane scans before deferring
 constexpr int kRowPrefix = kLaneCap;             // row entries in LDS when scans defer
 static_assert(kRowPrefix == kRowDist, "the stored distances cover the LDS row prefix");
@@ -439,13 +440,23 @@ __device__ __forceinline__ int full_scan(float x, float y, float z, int p, int K
     const float4 cp = cen[p];
     float bd = sq_dist(x, y, z, cp.x, cp.y, cp.z);
     int best = p;
-    for (int t = 0; t < K; ++t) {
-        if (t == p) continue;
-        const float4 ct = cen[t];
-        const float d = sq_dist(x, y, z, ct.x, ct.y, ct.z);
-        if (better_center(d, bd, t, best, p)) {
-            bd = d;
-            best = t;
+    // Centers in ascending order, kScanBatch at a time (reads issued
+    // together; cen has kMaxK entries, and those past K are not taken).
+    // Center p itself is taken too: it ties with the start, and the tie rule
+    // keeps p, so it never changes the result.
+    for (int t0 = 0; t0 < K; t0 += kScanBatch) {
+        float d[kScanBatch];
+#pragma unroll
+        for (int e = 0; e < kScanBatch; ++e) {
+            const float3 ct = *(const float3 *)(cen + t0 + e);
+            d[e] = sq_dist(x, y, z, ct.x, ct.y, ct.z);
+        }
+#pragma unroll
+        for (int e = 0; e < kScanBatch; ++e) {
+            if (t0 + e < K && better_center(d[e], bd, t0 + e, best, p)) {
+                bd = d[e];
+                best = t0 + e;
+            }
         }
     }
     ev += (uint32_t)K;
