@@ -362,6 +362,35 @@ def test_resume_equals_single_call():
     np.testing.assert_array_equal(a.history()[0], b.history()[0])
 
 
+@pytest.mark.parametrize("K", [16, 64, 256])
+def test_unpacked_sums_equal_packed(K):
+    # Counts x 300 push 255 * n_pixels past 2^32, so the centroid sums take
+    # four u64 per center instead of two packed ones.  Scaling every weight
+    # by the same factor leaves each center (sum c x / sum c, exact integer
+    # sums) unchanged, so memberships, palettes and evaluation counts must be
+    # identical to the unscaled run.
+    wsm = _wsm()
+    img = synth.workload_image("medium", 0)
+    g = _gpu_img(img)
+    col, cnt = wsm.reduce_colors(g)
+    n = img.shape[0] * img.shape[1]
+    scale = 300
+    assert 255 * n * scale >= 1 << 32 > 255 * n
+    _say("unpacked sums, medium seed 0, counts x", scale, "K", K)
+    pal = wsm.palette_from_indices(col, synth.init_indices(0, col.numel(), K))
+    a = wsm.init(col, cnt, n, pal)
+    a.iterate(6, 0.0)
+    b = wsm.init(col, cnt * scale, n * scale, pal)
+    b.iterate(6, 0.0)
+    assert np.array_equal(a.palette().cpu().numpy(), b.palette().cpu().numpy())
+    assert np.array_equal(a.membership().cpu().numpy(), b.membership().cpu().numpy())
+    sa, ea = a.history()
+    sb, eb = b.history()
+    np.testing.assert_array_equal(ea, eb)
+    np.testing.assert_allclose(sb, sa, rtol=1e-12)
+    assert a.info()["iters"] == b.info()["iters"] == 6
+
+
 # ---------------------------------------------------------------------------
 # Degenerate cases.
 
