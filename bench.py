@@ -108,8 +108,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of "
-                                   "it (see DESIGN.md for how the path would shard)",
+        print(json.dumps({"error": "the quantizer runs on one GPU; it has no multi-GPU form "
+                                   "(the path would shard by color-key range)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 

@@ -16,8 +16,8 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests skip themselves when no device is visible (CPU container);
-    # the GPU machine runs them with -m gpu.
+    # GPU tests skip themselves when no device is visible; on a machine with
+    # an MI355X they run with -m gpu.
     try:
         import torch
         has_gpu = torch.cuda.is_available()
