@@ -30,8 +30,7 @@ constexpr int kPass = kSearchThreads * kCpt;     // points per pass (4096)
 constexpr int kRowStride = kMaxK;                // bytes per row of M in device memory
 constexpr int kScanBatch = 8;                    // row entries fetched per scan step
 static_assert(kMaxK % kScanBatch == 0, "a batched full scan stays inside the center table");
-constexpr int kLaneCap = 32;                     // entries a lane scans before deferring
-constexpr int kRowPrefix = kLaneCap;             // row entries in LDS when scans defer
+constexpr int kRowPrefix = 32;                   // row head scanned flat (in LDS when scans defer)
 static_assert(kRowPrefix == kRowDist, "the stored distances cover the LDS row prefix");
 constexpr int kDeferCap = 512;                   // deferred scans per block
 constexpr int kDeferBatch = 8;                   // deferred scans a wave fetches rows for at once
@@ -233,20 +232,8 @@ __device__ __forceinline__ bool sm_scan_range(float x, float y, float z, int p, 
     return j >= n;
 }
 
-// The threshold of point x with previous center p; starts the scan state.
-__device__ __forceinline__ float sm_scan_begin(float x, float y, float z, int p,
-                                               const float4 *cen, float &bd, int &best,
-                                               uint32_t &ev) {
-    const float4 cp = cen[p];
-    const float prev = sq_dist(x, y, z, cp.x, cp.y, cp.z);
-    bd = prev;
-    best = p;
-    ev += 1;
-    return prev * kBreakScale;
-}
-
-// The whole scan of one point (the same steps as sm_scan_begin followed by
-// sm_scan_range over the whole row, in one loop).
+// The whole scan of one point over its row in LDS, in one loop: the start
+// at the previous center, then the row in batches as in sm_scan_range.
 __device__ __forceinline__ int sm_scan(float x, float y, float z, int p, int K,
                                        const float4 *cen, const uint8_t *Ms, int rs,
                                        float &best_d, uint32_t &ev) {

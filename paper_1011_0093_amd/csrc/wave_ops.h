@@ -105,29 +105,6 @@ __device__ __forceinline__ void wave_seg_sum2(int head, unsigned long long &a,
     seg_step_sum2<kDppRowBcast31>(lane, f, a, b);
 }
 
-template <int CTRL>
-__device__ __forceinline__ void seg_step_max(int lane, int &f, uint32_t &v) {
-    const int tf = dpp_i32<CTRL>(f);
-    const uint32_t tv = dpp_u32<CTRL>(v);
-    if (dpp_takes<CTRL>(lane)) {
-        if (!f) v = v > tv ? v : tv;
-        f |= tf;
-    }
-}
-
-// Segmented inclusive max (same segments as above).
-__device__ __forceinline__ uint32_t wave_seg_max(int head, uint32_t v) {
-    const int lane = threadIdx.x & 63;
-    int f = head;
-    seg_step_max<kDppRowShr1>(lane, f, v);
-    seg_step_max<kDppRowShr2>(lane, f, v);
-    seg_step_max<kDppRowShr4>(lane, f, v);
-    seg_step_max<kDppRowShr8>(lane, f, v);
-    seg_step_max<kDppRowBcast15>(lane, f, v);
-    seg_step_max<kDppRowBcast31>(lane, f, v);
-    return v;
-}
-
 // Inclusive maximum over the wave, in lane order.
 __device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
     const int lane = threadIdx.x & 63;
