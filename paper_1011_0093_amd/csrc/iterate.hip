@@ -242,19 +242,12 @@ __device__ __forceinline__ void prefetch_points(const IterArgs &a, uint32_t (&ke
 
 // Deferred sort-means scans (search kernel for K >= kDeferMinK): a point
 // whose scan goes past the row head that sm_scan_flat covers goes to an LDS
-// queue (while it has room; otherwise its lane carries on alone) and is
-// finished after the block's passes by a whole wave (sm_finish_wave), so
-// that the rare long scans do not hold their wave.  The first step of a
-// call, when every point starts from center 0 and most scans are long,
-// runs its own kernel (the full search), so the queue can stay short.
-struct DeferQueue {
-    uint32_t n;
-    uint32_t idx[kDeferCap];    // point index
-    uint32_t key[kDeferCap];    // its color and count
-    uint32_t cnt[kDeferCap];
-    uint32_t bd[kDeferCap];     // best distance so far (float bits)
-    uint32_t pjb[kDeferCap];    // next entry << 16 | previous center << 8 | best center
-};
+// queue (DeferQueue; while it has room, otherwise its lane carries on alone)
+// and is finished after the block's passes by a whole wave
+// (finish_deferred), so that the rare long scans do not hold their wave.
+// The first step of a call, when every point starts from center 0 and most
+// scans are long, runs its own kernel (the full search), so the queue can
+// stay short.
 
 // End of a search block: finishes the deferred scans (DEFER), adds the
 // block's sums into totals slot i % 3 and writes its SSE and evaluation
@@ -264,69 +257,28 @@ __device__ void finish_block(const IterArgs &a, int i, const float4 *cen, const 
                              unsigned long long *acc, double *dscr, unsigned long long *uscr,
                              DeferQueue *dq, double sse, uint32_t ev) {
     constexpr int NT = kSearchThreads;
-    constexpr int NW = NT / 64;
     constexpr int NACC = PACKED ? 2 : 4;
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int rs = lds_rows_stride<DEFER>(a.k);
     if (DEFER) {
-        // The deferred scans: wave w takes queue entries w, w + NW, ...; the
-        // row entries of the first step of kDeferBatch of them are loaded
-        // together (the rows past their LDS heads are in device memory).
         __syncthreads();
-        const uint32_t nd = dq->n < (uint32_t)kDeferCap ? dq->n : (uint32_t)kDeferCap;
-        for (uint32_t q0 = wave; q0 < nd; q0 += NW * kDeferBatch) {
-            int tf[kDeferBatch];
-#pragma unroll
-            for (int u = 0; u < kDeferBatch; ++u) {
-                const uint32_t q = q0 + (uint32_t)(u * NW);
-                tf[u] = 0;
-                if (q < nd) {
-                    const uint32_t pjb = dq->pjb[q];
-                    const int jj = (int)(pjb >> 16) + lane;
-                    const size_t row = (size_t)((pjb >> 8) & 0xFFu) * kRowStride;
-                    if (jj < a.k - 1) tf[u] = a.sv.rows[row + jj];
-                }
+        finish_deferred<NT>(a.k, cen, Ms, a.sv.rows, dq,
+                            [&](uint32_t idx, uint32_t k, uint32_t c, int best, float bd,
+                                uint32_t sev) {
+            ev += sev;
+            sse += (double)c * (double)bd;
+            a.sv.m[idx] = (uint8_t)best;
+            const unsigned long long cc = c;
+            const unsigned long long rr = (k >> 16) & 0xFFu, gg = (k >> 8) & 0xFFu, bb = k & 0xFFu;
+            if (PACKED) {
+                atomicAdd(&acc[best * 2 + 0], cc * rr | ((cc * gg) << 32));
+                atomicAdd(&acc[best * 2 + 1], cc * bb | (cc << 32));
+            } else {
+                atomicAdd(&acc[best * 4 + 0], cc * rr);
+                atomicAdd(&acc[best * 4 + 1], cc * gg);
+                atomicAdd(&acc[best * 4 + 2], cc * bb);
+                atomicAdd(&acc[best * 4 + 3], cc);
             }
-#pragma unroll
-            for (int u = 0; u < kDeferBatch; ++u) {
-                const uint32_t q = q0 + (uint32_t)(u * NW);
-                if (q >= nd) break;  // wave-uniform
-                const uint32_t idx = dq->idx[q], pjb = dq->pjb[q];
-                const int p = (int)((pjb >> 8) & 0xFFu);
-                int best = (int)(pjb & 0xFFu);
-                float bd = __uint_as_float(dq->bd[q]);
-                const uint32_t k = dq->key[q], c = dq->cnt[q];
-                float x, y, z;
-                unpack_key(k, x, y, z);
-                const float4 cp = cen[p];
-                const float thr = sq_dist(x, y, z, cp.x, cp.y, cp.z) * kBreakScale;
-                uint32_t sev = 0;
-                const RowView rv{Ms + p * rs, a.sv.rows + (size_t)p * kRowStride, kRowPrefix};
-                sm_finish_wave(x, y, z, p, a.k, cen, rv, thr, (int)(pjb >> 16), tf[u], bd, best,
-                               sev);
-                // one lane records the result (stores and LDS atomics only)
-                const bool me = lane == 0;
-                ev += me ? sev : 0u;
-                sse += me ? (double)c * (double)bd : 0.0;
-                if (me) {
-                    a.sv.m[idx] = (uint8_t)best;
-                    const unsigned long long cc = c;
-                    const unsigned long long rr = (k >> 16) & 0xFFu, gg = (k >> 8) & 0xFFu,
-                                             bb = k & 0xFFu;
-                    if (PACKED) {
-                        atomicAdd(&acc[best * 2 + 0], cc * rr | ((cc * gg) << 32));
-                        atomicAdd(&acc[best * 2 + 1], cc * bb | (cc << 32));
-                    } else {
-                        atomicAdd(&acc[best * 4 + 0], cc * rr);
-                        atomicAdd(&acc[best * 4 + 1], cc * gg);
-                        atomicAdd(&acc[best * 4 + 2], cc * bb);
-                        atomicAdd(&acc[best * 4 + 3], cc);
-                    }
-                }
-            }
-        }
+        });
     }
     __syncthreads();
     unsigned long long *T = a.sv.totals + (size_t)(i % 3) * kMaxK * 4;
@@ -520,7 +472,7 @@ __global__ __launch_bounds__(kSortThreads) void palette_rows_kernel(StateView sv
     __shared__ uint32_t rank[kMaxK];
     for (int c = threadIdx.x; c < K; c += kSortThreads) cen[c] = sv.pal[c];
     sort_row<kSortThreads>(cen, K, blockIdx.x, keys, rank, sv.rows + (size_t)blockIdx.x * kRowStride,
-                           nullptr);
+                           sv.rowd + (size_t)blockIdx.x * kRowDist);
 }
 
 // Sort-means step for K <= kFusedMaxK in one launch: every block applies

@@ -3,8 +3,11 @@
 //
 //   rows    the neighbour matrix M of the final palette, one row per block.
 //   assign  a sort-means scan of every unique color against the final palette,
-//           starting from the color's last membership, over an LDS copy of M
-//           (sm_block.h).  The palette index is scattered into a 2^24-entry
+//           starting from the color's last membership, as in the iteration
+//           search for large K (sm_block.h): the row heads of M and their
+//           distances in LDS, a wave's scans over them spread over its lanes,
+//           the rare longer ones finished by whole waves.  One block per CU.
+//           The palette index is scattered into a 2^24-entry
 //           byte table laid out in 4 x 4 x 4 color cells (lut_index);
 //           count * distance is summed per block for the MSE.
 //   gather  16 pixels per lane: three 16-byte loads, 16 table lookups, one
@@ -34,30 +37,43 @@ constexpr int kGatherPpt = 16;
 
 __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
     StateView sv, const uint32_t *__restrict__ colors, const uint32_t *__restrict__ counts,
-    int64_t n, int K, int64_t chunk, uint8_t *__restrict__ lut) {
-    __shared__ float4 cen[kMaxK];
-    __shared__ __align__(16) uint8_t Ms[kMaxK * kRowStride];
-    __shared__ double dscr[kSearchThreads / 64];
+    int64_t n, int K, uint8_t *__restrict__ lut) {
     constexpr int NT = kSearchThreads;
+    constexpr int NW = NT / 64;
+    __shared__ float4 cen[kMaxK];
+    __shared__ __align__(16) uint8_t Ms[kMaxK * kRowPrefix];  // row heads of M
+    __shared__ __align__(16) float Dd[kMaxK * kRowDist];      // and their distances
+    __shared__ FlatScratch fs[NW];
+    __shared__ DeferQueue dq;
+    __shared__ double dscr[NW];
     const int tid = threadIdx.x;
-    const int64_t start = (int64_t)blockIdx.x * chunk;
-    const int64_t end = (start + chunk) < n ? (start + chunk) : n;
-    const int rs = lds_row_stride(K);
+    const int lane = tid & 63, wave = tid >> 6;
+    // the 64-color chunks b, b + grid, b + 2 grid, ... (every block samples
+    // the whole key range, so the blocks get similar work); wave w takes
+    // chunk slot s0 + r * NW + w of pass s0
+    const int64_t grid = gridDim.x;
+    const int64_t chunks = (n + 63) / 64;
+    const int64_t ns = chunks > (int64_t)blockIdx.x ? (chunks - blockIdx.x + grid - 1) / grid : 0;
     for (int c = tid; c < K; c += NT) cen[c] = sv.pal[c];
-    load_rows<NT>(sv.rows, K, Ms);
+    RowRegs<NT> R;
+    fetch_rows<NT, true>(sv.rows, K, R);
+    store_rows<NT, true>(R, K, Ms);
+    for (int q = tid; q < K * (kRowDist / 4); q += NT) ((uint4 *)Dd)[q] = ((const uint4 *)sv.rowd)[q];
+    if (tid == 0) dq.n = 0u;
     __syncthreads();
     double acc = 0.0;
     uint32_t ev = 0;
-    for (int64_t base = start; base < end; base += kPass) {
+    for (int64_t s0 = 0; s0 < ns; s0 += kCpt * NW) {
         uint32_t key[kCpt], cnt[kCpt];
         int pm[kCpt];
 #pragma unroll
         for (int r = 0; r < kCpt; ++r) {
-            const int64_t idx = base + r * NT + tid;
+            const int64_t slot = s0 + r * NW + wave;
+            const int64_t idx = ((int64_t)blockIdx.x + slot * grid) * 64 + lane;
             key[r] = 0u;
             cnt[r] = 0u;
             pm[r] = 0;
-            if (idx < end) {
+            if (slot < ns && idx < n) {
                 key[r] = colors[idx];
                 cnt[r] = counts[idx];
                 pm[r] = sv.m[idx];
@@ -65,19 +81,49 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
         }
 #pragma unroll
         for (int r = 0; r < kCpt; ++r) {
-            if (base + r * NT >= end) break;  // block-uniform
-            const int64_t idx = base + r * NT + tid;
-            const bool valid = idx < end;
-            float x, y, z;
-            unpack_key(key[r], x, y, z);
-            if (valid) {
-                float bd;
-                const int best = sm_scan(x, y, z, pm[r], K, cen, Ms, rs, bd, ev);
+            if (s0 + r * NW >= ns) break;  // block-uniform
+            const int64_t slot = s0 + r * NW + wave;
+            const int64_t idx = ((int64_t)blockIdx.x + slot * grid) * 64 + lane;
+            const bool valid = slot < ns && idx < n;
+            // the wave's scans over the row heads together; one that goes
+            // past the head is deferred (or, with the queue full, carried on
+            // by its lane)
+            float thr, bd;
+            int best;
+            bool more;
+            sm_scan_flat(valid, key[r], pm[r], K, cen, Ms, Dd, fs[wave], thr, bd, best, ev, more);
+            bool done = true;
+            if (more) {
+                const uint32_t q = atomicAdd(&dq.n, 1u);
+                if (q < (uint32_t)kDeferCap) {
+                    dq.idx[q] = (uint32_t)idx;
+                    dq.key[q] = key[r];
+                    dq.cnt[q] = cnt[r];
+                    dq.bd[q] = __float_as_uint(bd);
+                    dq.pjb[q] = ((uint32_t)kRowPrefix << 16) | ((uint32_t)pm[r] << 8) |
+                                (uint32_t)best;
+                    done = false;
+                } else {
+                    float x, y, z;
+                    unpack_key(key[r], x, y, z);
+                    const RowView rv{Ms + pm[r] * kRowPrefix, sv.rows + (size_t)pm[r] * kRowStride,
+                                     kRowPrefix};
+                    int j = kRowPrefix;
+                    sm_scan_range(x, y, z, pm[r], K, cen, rv, thr, j, K, bd, best, ev);
+                }
+            }
+            if (valid && done) {
                 lut[lut_index_key(key[r])] = (uint8_t)best;
                 acc += (double)cnt[r] * (double)bd;
             }
         }
     }
+    __syncthreads();
+    finish_deferred<NT>(K, cen, Ms, sv.rows, &dq,
+                        [&](uint32_t, uint32_t k, uint32_t c, int best, float bd, uint32_t) {
+        lut[lut_index_key(k)] = (uint8_t)best;
+        acc += (double)c * (double)bd;
+    });
     const double s = block_sum_f64<NT>(acc, dscr);
     if (tid == 0) sv.map_part[blockIdx.x] = s;
 }
@@ -174,15 +220,13 @@ extern "C" int wsm_map_pixels(const wsm_problem *prob, const uint8_t *rgb, int64
     if (n_pixels < 1 || n_pixels != prob->n_pixels) return WSM_EINVAL;
     StateView sv = make_view(prob->state);
     (void)hipGetLastError();
-    // about one point per thread; at most kMaxGrid blocks
-    int64_t nb = (prob->n_points + kSearchThreads - 1) / kSearchThreads;
+    // the state's search grid (one block per CU, fewer for small tables)
+    int64_t nb = prob->grid;
+    if (nb < 1) nb = 1;
     if (nb > kMaxGrid) nb = kMaxGrid;
-    int64_t chunk = (prob->n_points + nb - 1) / nb;
-    chunk = (chunk + 63) / 64 * 64;
-    nb = (prob->n_points + chunk - 1) / chunk;
     if (wsm_internal_palette_rows(prob->state, prob->k, stream) != WSM_OK) return WSM_EHIP;
     WSM_LAUNCH(WSM_KERNEL_MAP_ASSIGN, map_assign_kernel, dim3((unsigned)nb), dim3(kSearchThreads),
-               stream, sv, prob->colors, prob->counts, prob->n_points, prob->k, chunk, lut);
+               stream, sv, prob->colors, prob->counts, prob->n_points, prob->k, lut);
     if (hipGetLastError() != hipSuccess) return WSM_EHIP;
     const int64_t per_block = (int64_t)kMapThreads * kGatherPpt;
     const int64_t gb = (n_pixels + per_block - 1) / per_block;

@@ -399,6 +399,65 @@ __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, in
     if (valid) ev += 1u + (uint32_t)n;
 }
 
+// Queue of a block's deferred scans (LDS): points whose scan goes past the
+// row head, with the state of the scan so far.
+struct DeferQueue {
+    uint32_t n;
+    uint32_t idx[kDeferCap];    // point index
+    uint32_t key[kDeferCap];    // its color and count
+    uint32_t cnt[kDeferCap];
+    uint32_t bd[kDeferCap];     // best distance so far (float bits)
+    uint32_t pjb[kDeferCap];    // next entry << 16 | previous center << 8 | best center
+};
+
+// Finishes a block's deferred scans: wave w takes queue entries w, w + NW,
+// ..., each with sm_finish_wave over the row past its head (Ms holds row
+// heads of kRowPrefix entries, rows the whole rows in device memory); the
+// row entries of the first step of kDeferBatch entries are loaded together.
+// For each finished point lane 0 of the wave calls rec(idx, key, count,
+// best, best distance, evaluations made).  All threads call it, after a
+// barrier that follows the last push to the queue.
+template <int NT, typename Rec>
+__device__ __forceinline__ void finish_deferred(int K, const float4 *cen, const uint8_t *Ms,
+                                                const uint8_t *__restrict__ rows,
+                                                const DeferQueue *dq, Rec &&rec) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t nd = dq->n < (uint32_t)kDeferCap ? dq->n : (uint32_t)kDeferCap;
+    for (uint32_t q0 = wave; q0 < nd; q0 += NW * kDeferBatch) {
+        int tf[kDeferBatch];
+#pragma unroll
+        for (int u = 0; u < kDeferBatch; ++u) {
+            const uint32_t q = q0 + (uint32_t)(u * NW);
+            tf[u] = 0;
+            if (q < nd) {
+                const uint32_t pjb = dq->pjb[q];
+                const int jj = (int)(pjb >> 16) + lane;
+                const size_t row = (size_t)((pjb >> 8) & 0xFFu) * kRowStride;
+                if (jj < K - 1) tf[u] = rows[row + jj];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kDeferBatch; ++u) {
+            const uint32_t q = q0 + (uint32_t)(u * NW);
+            if (q >= nd) break;  // wave-uniform
+            const uint32_t idx = dq->idx[q], pjb = dq->pjb[q];
+            const int p = (int)((pjb >> 8) & 0xFFu);
+            int best = (int)(pjb & 0xFFu);
+            float bd = __uint_as_float(dq->bd[q]);
+            const uint32_t k = dq->key[q], c = dq->cnt[q];
+            float x, y, z;
+            unpack_key(k, x, y, z);
+            const float4 cp = cen[p];
+            const float thr = sq_dist(x, y, z, cp.x, cp.y, cp.z) * kBreakScale;
+            uint32_t sev = 0;
+            const RowView rv{Ms + p * kRowPrefix, rows + (size_t)p * kRowStride, kRowPrefix};
+            sm_finish_wave(x, y, z, p, K, cen, rv, thr, (int)(pjb >> 16), tf[u], bd, best, sev);
+            if (lane == 0) rec(idx, k, c, best, bd, sev);  // stores and LDS atomics only
+        }
+    }
+}
+
 // The number of evaluations the sort-means scan of x from p makes: 1 (the
 // previous center) + the number of row entries before the first one at or
 // past the threshold.  Row p is sorted by d(c_p, c_t)^2, so a binary search
