@@ -35,15 +35,20 @@ __device__ __forceinline__ uint32_t lut_index_key(uint32_t key) {
 }
 constexpr int kGatherPpt = 16;
 
+// FLAT (K >= kDeferMinK, as in the iteration search): flattened scans over
+// the row heads, long scans deferred.  Otherwise each lane scans its color's
+// whole row in LDS (sm_scan).
+template <bool FLAT>
 __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
     StateView sv, const uint32_t *__restrict__ colors, const uint32_t *__restrict__ counts,
     int64_t n, int K, uint8_t *__restrict__ lut) {
     constexpr int NT = kSearchThreads;
     constexpr int NW = NT / 64;
     __shared__ float4 cen[kMaxK];
-    __shared__ __align__(16) uint8_t Ms[kMaxK * kRowPrefix];  // row heads of M
-    __shared__ __align__(16) float Dd[kMaxK * kRowDist];      // and their distances
-    __shared__ FlatScratch fs[NW];
+    // rows of M: their heads (FLAT) or whole
+    __shared__ __align__(16) uint8_t Ms[kMaxK * (FLAT ? kRowPrefix : kRowStride)];
+    __shared__ __align__(16) float Dd[FLAT ? kMaxK * kRowDist : 4];  // the heads' distances
+    __shared__ FlatScratch fs[FLAT ? NW : 1];
     __shared__ DeferQueue dq;
     __shared__ double dscr[NW];
     const int tid = threadIdx.x;
@@ -56,9 +61,11 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
     const int64_t ns = chunks > (int64_t)blockIdx.x ? (chunks - blockIdx.x + grid - 1) / grid : 0;
     for (int c = tid; c < K; c += NT) cen[c] = sv.pal[c];
     RowRegs<NT> R;
-    fetch_rows<NT, true>(sv.rows, K, R);
-    store_rows<NT, true>(R, K, Ms);
-    for (int q = tid; q < K * (kRowDist / 4); q += NT) ((uint4 *)Dd)[q] = ((const uint4 *)sv.rowd)[q];
+    fetch_rows<NT, FLAT>(sv.rows, K, R);
+    store_rows<NT, FLAT>(R, K, Ms);
+    if (FLAT)
+        for (int q = tid; q < K * (kRowDist / 4); q += NT)
+            ((uint4 *)Dd)[q] = ((const uint4 *)sv.rowd)[q];
     if (tid == 0) dq.n = 0u;
     __syncthreads();
     double acc = 0.0;
@@ -88,12 +95,19 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
             // the wave's scans over the row heads together; one that goes
             // past the head is deferred (or, with the queue full, carried on
             // by its lane)
-            float thr, bd;
-            int best;
-            bool more;
-            sm_scan_flat(valid, key[r], pm[r], K, cen, Ms, Dd, fs[wave], thr, bd, best, ev, more);
+            float thr = 0.f, bd = 0.f;
+            int best = 0;
+            bool more = false;
+            if (FLAT) {
+                sm_scan_flat(valid, key[r], pm[r], K, cen, Ms, Dd, fs[wave], thr, bd, best, ev,
+                             more);
+            } else if (valid) {
+                float x, y, z;
+                unpack_key(key[r], x, y, z);
+                best = sm_scan(x, y, z, pm[r], K, cen, Ms, lds_row_stride(K), bd, ev);
+            }
             bool done = true;
-            if (more) {
+            if (FLAT && more) {
                 const uint32_t q = atomicAdd(&dq.n, 1u);
                 if (q < (uint32_t)kDeferCap) {
                     dq.idx[q] = (uint32_t)idx;
@@ -118,12 +132,14 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
             }
         }
     }
-    __syncthreads();
-    finish_deferred<NT>(K, cen, Ms, sv.rows, &dq,
-                        [&](uint32_t, uint32_t k, uint32_t c, int best, float bd, uint32_t) {
-        lut[lut_index_key(k)] = (uint8_t)best;
-        acc += (double)c * (double)bd;
-    });
+    if (FLAT) {
+        __syncthreads();
+        finish_deferred<NT>(K, cen, Ms, sv.rows, &dq,
+                            [&](uint32_t, uint32_t k, uint32_t c, int best, float bd, uint32_t) {
+            lut[lut_index_key(k)] = (uint8_t)best;
+            acc += (double)c * (double)bd;
+        });
+    }
     const double s = block_sum_f64<NT>(acc, dscr);
     if (tid == 0) sv.map_part[blockIdx.x] = s;
 }
@@ -225,8 +241,9 @@ extern "C" int wsm_map_pixels(const wsm_problem *prob, const uint8_t *rgb, int64
     if (nb < 1) nb = 1;
     if (nb > kMaxGrid) nb = kMaxGrid;
     if (wsm_internal_palette_rows(prob->state, prob->k, stream) != WSM_OK) return WSM_EHIP;
-    WSM_LAUNCH(WSM_KERNEL_MAP_ASSIGN, map_assign_kernel, dim3((unsigned)nb), dim3(kSearchThreads),
-               stream, sv, prob->colors, prob->counts, prob->n_points, prob->k, lut);
+    const auto assign = prob->k >= kDeferMinK ? map_assign_kernel<true> : map_assign_kernel<false>;
+    WSM_LAUNCH(WSM_KERNEL_MAP_ASSIGN, assign, dim3((unsigned)nb), dim3(kSearchThreads), stream, sv,
+               prob->colors, prob->counts, prob->n_points, prob->k, lut);
     if (hipGetLastError() != hipSuccess) return WSM_EHIP;
     const int64_t per_block = (int64_t)kMapThreads * kGatherPpt;
     const int64_t gb = (n_pixels + per_block - 1) / per_block;
