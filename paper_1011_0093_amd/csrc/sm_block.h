@@ -488,8 +488,11 @@ __device__ __forceinline__ int full_scan(float x, float y, float z, int p, int K
     int best = p;
     // Centers in ascending order, kScanBatch at a time (reads issued
     // together; cen has kMaxK entries, and those past K are not taken).
-    // Center p itself is taken too: it ties with the start, and the tie rule
-    // keeps p, so it never changes the result.
+    // Under the tie rule (dist, k != p, k) a center replaces the best exactly
+    // when it is strictly nearer: a later center that ties the best has a
+    // higher index than it, or the best is still p, and both are kept; and
+    // once the best has left p it is strictly nearer than p, so p (taken in
+    // its turn, tying with the start) cannot tie it again.
     for (int t0 = 0; t0 < K; t0 += kScanBatch) {
         float d[kScanBatch];
 #pragma unroll
@@ -499,7 +502,7 @@ __device__ __forceinline__ int full_scan(float x, float y, float z, int p, int K
         }
 #pragma unroll
         for (int e = 0; e < kScanBatch; ++e) {
-            if (t0 + e < K && better_center(d[e], bd, t0 + e, best, p)) {
+            if (t0 + e < K && d[e] < bd) {
                 bd = d[e];
                 best = t0 + e;
             }
