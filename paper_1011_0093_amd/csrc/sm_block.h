@@ -32,7 +32,7 @@ constexpr int kScanBatch = 8;                    // row entries fetched per scan
 static_assert(kMaxK % kScanBatch == 0, "a batched full scan stays inside the center table");
 constexpr int kRowPrefix = 32;                   // row head scanned flat (in LDS when scans defer)
 static_assert(kRowPrefix == kRowDist, "the stored distances cover the LDS row prefix");
-constexpr int kDeferCap = 512;                   // deferred scans per block
+constexpr int kDeferCap = 1024;                  // deferred scans per block
 constexpr int kDeferBatch = 8;                   // deferred scans a wave fetches rows for at once
 constexpr int kDeferMinK = 128;                  // smallest K whose search defers
 constexpr int kFusedMaxK = 32;                   // largest K sorted inside the search block
