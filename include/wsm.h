@@ -183,9 +183,10 @@ int wsm_map_pixels(const wsm_problem *prob, const uint8_t *rgb,
  * HIP runtime create the graph (host work of a few milliseconds; the runtime
  * may reserve device memory for it).  Up to 64 argument sets are kept until
  * the process ends; further sets, calls on a stream that is being captured,
- * and calls while a timing hook is attached launch directly.  wsm_set_graph_replay(0) makes every call launch
- * directly, (1) restores replay; it returns the previous setting.  Results
- * are the same either way. */
+ * and calls while a timing hook is attached launch directly.
+ * wsm_set_graph_replay(0) makes every call launch directly, (1) restores
+ * replay; it returns the previous setting.  Results are the same either
+ * way. */
 int wsm_set_graph_replay(int enable);
 
 /* ------------------------------------------------------------------ */
