@@ -504,6 +504,50 @@ def test_large_lockstep_and_map_sample():
     assert float(mse.item()) == pytest.approx(cmse, rel=MSE_RTOL)
 
 
+def test_identical_centers_fill_the_deferral_queue():
+    # All 256 centers start at one color.  The first step keeps every color
+    # at center 0 (all distances tie); its update moves center 0 and leaves
+    # the other 255 where they were, so in the second step every row is a
+    # run of equal distances and nearly every scan covers its whole row.  At
+    # 4096x4096 (about 7,450 colors per search block) that is more long scans
+    # than a block's deferral queue holds, so both the deferred finish and
+    # the in-place continuation run, in the search and in the pixel map.
+    wsm = _wsm()
+    img = synth.workload_image("large", 0)
+    _say("large 4096x4096 seed 0 K=256, all centers at one color: 2 steps + map sample")
+    g = _gpu_img(img)
+    col, cnt = wsm.reduce_colors(g)
+    colors, counts = _u32(col), _u32(cnt)
+    n_pix = img.shape[0] * img.shape[1]
+    K = 256
+    pal = wsm.palette_from_indices(col, [len(colors) // 2] * K)
+    one = wsm.init(col, cnt, n_pix, pal)
+    one.iterate(1, 0.0)
+    m1 = one.membership().cpu().numpy()
+    c1 = one.palette().cpu().numpy().astype(np.float64)
+    assert (m1 == 0).all()
+    two = wsm.init(col, cnt, n_pix, pal)
+    two.iterate(2, 0.0)
+    assert two.info()["iters"] == 2
+    m2 = two.membership().cpu().numpy()
+    m_ref, mind, ev_ref = oracle.search_step(colors, c1, m1)
+    x = unpack(colors)
+    sel = np.random.default_rng(0).choice(len(colors), size=200000, replace=False)
+    check_assignment(x[sel], c1, m2[sel], m_ref[sel])
+    sse, ev = two.history()
+    assert ev_ref > 100 * len(colors)  # most scans run over the whole row
+    assert abs(int(ev[1]) - ev_ref) <= max(2, 1e-3 * ev_ref), (ev[1], ev_ref)
+    assert sse[1] == pytest.approx(oracle.weighted_sse(counts, n_pix, mind), rel=1e-6)
+    idx, _, mse = wsm.map_pixels(two, g)
+    c2 = two.palette().cpu().numpy().astype(np.float64)
+    psel = np.random.default_rng(1).choice(n_pix, size=200000, replace=False)
+    sub = img.reshape(-1, 3)[psel]
+    ref_idx, _ = oracle.map_pixels(sub[:, None, :], colors, m2, c2)
+    check_assignment(sub.astype(np.float64), c2, idx.cpu().numpy()[psel], ref_idx)
+    _, cmse = oracle.assign_colors(colors, counts, n_pix, m2, c2)
+    assert float(mse.item()) == pytest.approx(cmse, rel=MSE_RTOL)
+
+
 # ---------------------------------------------------------------------------
 # Launch replay from HIP graphs: bit-identical to direct launches.
 
