@@ -462,7 +462,8 @@ def test_invalid_arguments_raise():
 # ---------------------------------------------------------------------------
 # Pixel mapping.
 
-@pytest.mark.parametrize("name,seed,K", [("small", 0, 32), ("medium", 2, 256)])
+@pytest.mark.parametrize("name,seed,K", [("small", 0, 32), ("medium", 0, 64), ("small", 1, 128),
+                                         ("medium", 2, 256)])
 def test_map_against_oracle(name, seed, K):
     wsm = _wsm()
     img = synth.workload_image(name, seed)
