@@ -29,6 +29,7 @@ constexpr int kCpt = 4;                          // points per thread per pass
 constexpr int kPass = kSearchThreads * kCpt;     // points per pass (4096)
 constexpr int kRowStride = kMaxK;                // bytes per row of M in device memory
 constexpr int kScanBatch = 8;                    // row entries fetched per scan step
+static_assert(kScanBatch == 8, "a scan batch is one 8-byte word of a row, read aligned");
 static_assert(kMaxK % kScanBatch == 0, "a batched full scan stays inside the center table");
 constexpr int kRowPrefix = 32;                   // row head scanned flat (in LDS when scans defer)
 static_assert(kRowPrefix == kRowDist, "the stored distances cover the LDS row prefix");
