@@ -177,6 +177,17 @@ def test_lockstep_medium(K):
     print(stats[-1])
 
 
+@pytest.mark.parametrize("K", [2, 31, 97, 127, 128, 129, 200, 255])
+def test_lockstep_k_around_kernel_switches(K):
+    # K <= 32: one fused launch; 33..127: rows + lane scans; >= 128: rows +
+    # flattened scans with deferral.  Odd K give rows whose length is not a
+    # multiple of the scan batch or of the 32-entry head.
+    img = synth.workload_image("medium", 1)
+    _say("lockstep medium seed 1 K", K)
+    stats = _lockstep(img, K, 1, 3)
+    print(stats[-1])
+
+
 @pytest.mark.parametrize("K", [128, 256])
 def test_lockstep_small_many_centers(K):
     """K = 128 is the first K whose search defers long scans; on the small
