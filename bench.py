@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -45,6 +46,16 @@ HBM_PEAK_GBS = 8000.0
 SEARCH_TRAFFIC_BYTES = 3540284
 SEARCH_TRAFFIC_SRC = "ed9ca8dacc69ed8e"
 _KERNEL_SOURCES = ("iterate.hip", "sm_block.h", "wave_ops.h", "wsm_internal.h")
+
+# The same for the 4096x4096 reduction (partition + compaction, bytes per
+# call) and pixel gather (bytes per launch)
+# (profiles/reduce_map_4096x4096_traffic.md).
+REDUCE_TRAFFIC_BYTES = 188613911
+REDUCE_TRAFFIC_SRC = "7a85f2a8e6e8d236"
+GATHER_TRAFFIC_BYTES = 106184633
+GATHER_TRAFFIC_SRC = "7b9861d30065b11f"
+_REDUCE_SOURCES = ("reduce.hip", "wave_ops.h", "wsm_internal.h")
+_MAP_SOURCES = ("map.hip", "sm_block.h", "wave_ops.h", "wsm_internal.h")
 
 
 def _code_only(text: str) -> str:
@@ -71,12 +82,13 @@ def _code_only(text: str) -> str:
     return "\n".join(line for line in lines if line)
 
 
-def kernel_sources_hash() -> str:
-    """sha256 (first 16 hex digits) of the search kernel's sources, comments
-    and blank lines removed, so that a comment edit keeps the counters."""
+def kernel_sources_hash(names=None) -> str:
+    """sha256 (first 16 hex digits) of kernel sources (default: the search
+    kernel's), comments and blank lines removed, so that a comment edit keeps
+    the counters."""
     import hashlib
     h = hashlib.sha256()
-    for name in _KERNEL_SOURCES:
+    for name in names or _KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1011_0093_amd", "csrc", name), encoding="utf-8") as f:
             h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
@@ -173,12 +185,16 @@ def main():
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(args.steps):
+    for s_ in range(args.steps):
         n_unique, out = step()
+        marks[s_].record(stream)
     e1.record(stream)
     torch.cuda.synchronize()
+    step_ms = [e0.elapsed_time(marks[0])] + [marks[s_ - 1].elapsed_time(marks[s_])
+                                              for s_ in range(1, args.steps)]
     wall = time.perf_counter() - t0
     ms_step = e0.elapsed_time(e1) / args.steps
     ms_step_wall = wall * 1000.0 / args.steps
@@ -190,8 +206,10 @@ def main():
         info = st.info()
         sse, ev = st.history()
         color_iters += n_unique * info["iters"]
+        mse_v = float(mse.item())
         per_k[str(K)] = dict(iters=info["iters"], converged=info["converged"],
-                             mse=float(mse.item()),
+                             mse=mse_v,
+                             psnr_db=10.0 * math.log10(255.0 ** 2 / mse_v) if mse_v > 0 else None,
                              evals_per_color_first=float(ev[0] / n_unique),
                              evals_per_color_last=float(ev[-1] / n_unique))
     value = color_iters / (ms_step * 1e-3)
@@ -300,6 +318,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "ms_per_step_wall": ms_step_wall,
+        "ms_per_step_p10_p50_p90": [float(np.percentile(step_ms, q)) for q in (10, 50, 90)],
         "images_per_s": len(Ks) / (ms_step * 1e-3),
         "higher_is_better": True,
         "scaling": "weak",
@@ -333,6 +352,20 @@ def bench_large(args, torch, wsm, synth):
     ws = torch.empty(wsm.reduce_workspace_bytes(N), dtype=torch.uint8, device=dev)
     lut = torch.empty(1 << 24, dtype=torch.uint8, device=dev)
     reps = 10
+    # a plain device copy of 256 MiB: the bandwidth this GPU reaches on a
+    # stream of reads and writes, to set the fractions below against
+    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2.0 * src.numel() * 4 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
     for _ in range(2):
         wsm.reduce_colors_into(img, colors, counts, nu, ws)
     torch.cuda.synchronize()
@@ -365,15 +398,24 @@ def bench_large(args, torch, wsm, synth):
     red_bytes = 3.0 * N + 8.0 * n_unique
     map_bytes = 4.0 * N
     red_t = t_part + t_comp
+    red_gbs = red_bytes / (red_t * 1e-3) / 1e9
+    map_gbs = map_bytes / (t_gather * 1e-3) / 1e9
+    red_traffic = REDUCE_TRAFFIC_BYTES if (
+        REDUCE_TRAFFIC_BYTES is not None
+        and kernel_sources_hash(_REDUCE_SOURCES) == REDUCE_TRAFFIC_SRC) else None
+    map_traffic = GATHER_TRAFFIC_BYTES if (
+        GATHER_TRAFFIC_BYTES is not None
+        and kernel_sources_hash(_MAP_SOURCES) == GATHER_TRAFFIC_SRC) else None
     out = dict(
         workload="4096x4096 sinusoid-field image (seed 0, noise sigma 12), K=256",
-        n_pixels=N, n_unique=n_unique,
-        reduce=dict(bound="hbm", achieved=red_bytes / (red_t * 1e-3) / 1e9, peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=red_bytes / (red_t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        n_pixels=N, n_unique=n_unique, copy_gbs=copy_gbs,
+        reduce=dict(bound="hbm", achieved=red_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=red_gbs / HBM_PEAK_GBS, frac_of_copy=red_gbs / copy_gbs,
+                    traffic=red_traffic, traffic_unit="bytes per call",
                     partition_us=t_part * 1e3, compact_us=t_comp * 1e3, bytes=red_bytes),
-        map_gather=dict(bound="hbm", achieved=map_bytes / (t_gather * 1e-3) / 1e9,
-                        peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=map_bytes / (t_gather * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        map_gather=dict(bound="hbm", achieved=map_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=map_gbs / HBM_PEAK_GBS, frac_of_copy=map_gbs / copy_gbs,
+                        traffic=map_traffic, traffic_unit="bytes per launch",
                         avg_launch_us=t_gather * 1e3, bytes=map_bytes),
         map_assign_us=t_assign * 1e3,
         iterate_10_ms=t_iter[0].elapsed_time(t_iter[1]),
