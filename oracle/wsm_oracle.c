@@ -179,17 +179,22 @@ int64_t oracle_search_step(const uint32_t *colors, int64_t n, const double *c,
 
 /* ------------------------------------------------------------------ */
 /* Alg. 2, center update: c_k = (sum_{m[i]=k} w_i x_i) / (sum_{m[i]=k} w_i)
- * with the weights of Sec. 2 ("sample weighting"), w_i = count_i / N.
- * An empty cluster keeps its center (R5).  `c` is updated in place. */
+ * with the weights of Sec. 2 ("sample weighting"), w_i = count_i / N.  The
+ * factor 1/N is common to the numerator and the denominator, so the center is
+ * the count-weighted mean (sum count_i x_i) / (sum count_i).  Both sums are
+ * integers below 2^53, exact in double, so the division is the only rounding
+ * and the center is the correctly rounded value of the weighted mean.  An
+ * empty cluster keeps its center (R5).  `c` is updated in place. */
 void oracle_update_step(const uint32_t *colors, const uint32_t *counts,
                         int64_t n, int64_t n_pixels, const uint8_t *m, int K,
                         double *c)
 {
+    (void)n_pixels;  /* the common factor 1/N of the weights cancels */
     double *sum = (double *)calloc((size_t)K * 4, sizeof(double));
     for (int64_t i = 0; i < n; ++i) {
         double x[3];
         unpack_color(colors[i], x);
-        double w = (double)counts[i] / (double)n_pixels;
+        double w = (double)counts[i];
         int k = m[i];
         sum[4 * k + 0] += w * x[0];
         sum[4 * k + 1] += w * x[1];

@@ -26,7 +26,7 @@ MUTATIONS = [
     ("tie_ignores_previous", "(dist == best_d && best != p && t < best)", "(dist == best_d && t < best)"),
     ("channel_term_swapped", "return d0 * d0 + d1 * d1 + d2 * d2;", "return d0 * d0 + d1 * d0 + d2 * d2;"),
     ("channel_term_dropped", "return d0 * d0 + d1 * d1 + d2 * d2;", "return d0 * d0 + d1 * d1;"),
-    ("unweighted_update", "double w = (double)counts[i] / (double)n_pixels;", "double w = 1.0 / (double)n_pixels;"),
+    ("unweighted_update", "double w = (double)counts[i];", "double w = 1.0;"),
     ("empty_cluster_not_kept", "if (sum[4 * k + 3] > 0.0) {\n            c[3 * k + 0]", "if (1) {\n            c[3 * k + 0]"),
     ("stop_rule_from_first_iter", "(t >= 2 && (prev_sse - sse) / sse <= eps)", "(t >= 1 && (prev_sse - sse) / sse <= eps)"),
     ("stop_rule_sign", "(prev_sse - sse) / sse <= eps)", "(sse - prev_sse) / sse <= eps)"),

@@ -168,8 +168,10 @@ def test_wsm_trajectory_equals_exact_lloyd(seed):
     for t, rec in enumerate(hist):
         assert r["sse"][t] == pytest.approx(float(rec["sse"]), rel=1e-12, abs=1e-12)
     assert r["m"].tolist() == hist[-1]["m"]
-    np.testing.assert_allclose(r["centers"], np.array([[float(v) for v in c] for c in hist[-1]["centers"]]),
-                               rtol=1e-12, atol=1e-12)
+    # the centers come from exact integer sums with one division: they are the
+    # correctly rounded exact weighted means, bit for bit
+    exact = np.array([[float(v) for v in c] for c in hist[-1]["centers"]])
+    np.testing.assert_array_equal(r["centers"], exact)
 
 
 def test_wsm_equals_kmeans_on_pixels():
@@ -184,7 +186,8 @@ def test_wsm_equals_kmeans_on_pixels():
     km = oracle.kmeans_pixels(img, init, 20, 1e-4)
     assert r["iters"] == km["iters"]
     np.testing.assert_allclose(r["sse"], km["sse"], rtol=1e-12)
-    np.testing.assert_allclose(r["centers"], km["centers"], rtol=1e-12, atol=1e-12)
+    # both compute each center as (exact integer sum) / (exact count)
+    np.testing.assert_array_equal(r["centers"], km["centers"])
     pix = [tuple(int(v) for v in p) for p in img.reshape(-1, 3)]
     hist, conv = lloyd(pix, [1] * len(pix), [tuple(p) for p in init], 20, 1e-4)
     assert len(hist) == r["iters"]
@@ -237,8 +240,8 @@ def test_exactly_k_colors_reach_zero_error_in_one_iteration():
     r = oracle.wsm(col, cnt, 900, init, 50, 1e-4)
     assert r["iters"] == 1 and r["converged"] and r["sse"][0] == 0.0
     idx, mse = oracle.map_pixels(img, col, r["m"], r["centers"])
-    # w = count/N weights make the update (w x)/w, exact up to float64 rounding
-    assert mse < 1e-20
+    # each center is (count x) / count, exactly the color
+    assert mse == 0.0
     np.testing.assert_allclose(r["centers"][idx], img.reshape(-1, 3).astype(float), rtol=1e-14)
 
 
