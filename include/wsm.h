@@ -10,11 +10,11 @@
  * Conventions for every function below:
  *   - Pointers are DEVICE pointers unless the comment says "host".
  *   - All device work is enqueued asynchronously on `stream`; no function
- *     allocates device memory, frees it, or synchronizes the host (the one
- *     exception is the HIP graph the runtime builds when an iterate call
- *     repeats earlier arguments; see wsm_set_graph_replay).  Every buffer is owned
- *     by the caller and must stay valid until the enqueued work has
- *     finished.
+ *     allocates device memory, frees it, or synchronizes the host, except the
+ *     explicit graph handles (wsm_iterate_graph_*), which the caller creates
+ *     and destroys.  The library holds no state between calls (apart from
+ *     the measurement hook at the end).  Every buffer is owned by the caller
+ *     and must stay valid until the enqueued work has finished.
  *   - Return value: WSM_OK (0) or a negative wsm_status.  Arguments are fully
  *     validated on the host before anything is enqueued; on error nothing is
  *     enqueued and no output is written.  WSM_EHIP reports a failed launch.
@@ -139,7 +139,12 @@ int wsm_iterate_full(const wsm_problem *prob, int max_iters, double eps,
                      hipStream_t stream);
 
 /* Device pointers into a state.  palette: float4[k] (R,G,B,0) after the
- * last update; membership: uint8[n_points]; sse_history / evals_history:
+ * last update; palette64: the same centers in float64, double4[k] (R,G,B,0)
+ * -- each the correctly rounded count-weighted mean of its cluster (Alg. 2,
+ * last loop), of which palette is the float32 rounding; the searches choose
+ * centers as float64 arithmetic on palette64 does, with ties kept by the
+ * previous center, then the lower index; membership: uint8[n_points];
+ * sse_history / evals_history:
  * [WSM_HISTORY], entry t-1 for iteration t (SSE_t normalised by n_pixels,
  * i.e. the MSE of the palette entering iteration t; evals = the distance
  * evaluations of Alg. 2's scan, summed over the points: 1 + the centers
@@ -152,6 +157,7 @@ typedef struct wsm_views {
     const double *sse_history;
     const int64_t *evals_history;
     const int32_t *info;
+    const double *palette64;
 } wsm_views;
 int wsm_state_views(const wsm_problem *prob, wsm_views *views /* host */);
 
@@ -175,19 +181,27 @@ int wsm_map_pixels(const wsm_problem *prob, const uint8_t *rgb,
 /* ------------------------------------------------------------------ */
 /* Launch replay (not part of the method).  wsm_iterate and
  * wsm_iterate_full enqueue a fixed sequence of kernel launches that depends
- * only on their arguments.  By default the library remembers each set of
- * arguments (state, points, K, grid, eps, max_iters); the second call with
- * the same set records the sequence into a HIP graph, on a stream of its
- * own, and that call and every later one replay the graph on `stream`,
- * which shortens the gaps between the launches.  The recording call lets the
- * HIP runtime create the graph (host work of a few milliseconds; the runtime
- * may reserve device memory for it).  Up to 64 argument sets are kept until
- * the process ends; further sets, calls on a stream that is being captured,
- * and calls while a timing hook is attached launch directly.
- * wsm_set_graph_replay(0) makes every call launch directly, (1) restores
- * replay; it returns the previous setting.  Results are the same either
- * way. */
-int wsm_set_graph_replay(int enable);
+ * only on their arguments, and they can be captured into a HIP graph by the
+ * caller like any stream work.  These calls do that for the caller, with an
+ * opaque handle the caller owns:
+ *   - create records the sequence of wsm_iterate (full = 0) or
+ *     wsm_iterate_full (full != 0) for prob, max_iters and eps into a graph,
+ *     on a stream of its own that it destroys again, and instantiates it
+ *     (host work of a few milliseconds; the runtime may reserve device
+ *     memory for the graph).  Nothing runs on the device.  Validation as for
+ *     wsm_iterate; *graph is NULL on error.
+ *   - launch enqueues the whole sequence on `stream`; the effect is that of
+ *     the corresponding iterate call with the same arguments.  The state,
+ *     points and prob's buffers must be the ones the graph was created for
+ *     (re-initialising the same state with wsm_init is allowed).
+ *   - destroy releases the graph; the caller must not launch it afterwards.
+ *     Work already enqueued is not affected.
+ * A handle may be launched from any thread, but not by two threads at once. */
+typedef struct wsm_graph wsm_graph;
+int wsm_iterate_graph_create(const wsm_problem *prob, int max_iters, double eps,
+                             int full, wsm_graph **graph /* host, out */);
+int wsm_iterate_graph_launch(wsm_graph *graph, hipStream_t stream);
+int wsm_iterate_graph_destroy(wsm_graph *graph);
 
 /* ------------------------------------------------------------------ */
 /* Measurement support (not part of the method).  While attached, every

@@ -21,7 +21,7 @@ import torch  # imported before the library so both share one HIP runtime
 
 __all__ = [
     "WsmError", "library_path", "reduce_colors", "reduce_colors_into",
-    "State", "init", "init_pixels", "map_pixels", "palette_from_indices",
+    "State", "IterateGraph", "init", "init_pixels", "map_pixels", "palette_from_indices",
     "quantize", "MAX_K", "HISTORY",
 ]
 
@@ -60,6 +60,7 @@ class _Views(ctypes.Structure):
         ("sse_history", ctypes.c_void_p),
         ("evals_history", ctypes.c_void_p),
         ("info", ctypes.c_void_p),
+        ("palette64", ctypes.c_void_p),
     ]
 
 
@@ -91,11 +92,14 @@ def _load():
     lib.wsm_timing_attach.argtypes = [I32, I32]
     lib.wsm_timing_read.argtypes = [ctypes.POINTER(ctypes.c_float), I32, ctypes.POINTER(I32)]
     lib.wsm_timing_detach.argtypes = []
-    lib.wsm_set_graph_replay.argtypes = [I32]
+    lib.wsm_iterate_graph_create.argtypes = [PP, I32, D, I32, ctypes.POINTER(P)]
+    lib.wsm_iterate_graph_launch.argtypes = [P, P]
+    lib.wsm_iterate_graph_destroy.argtypes = [P]
     for f in ("wsm_reduce_workspace_bytes", "wsm_reduce_colors", "wsm_state_bytes", "wsm_init",
               "wsm_init_pixels", "wsm_iterate", "wsm_iterate_full", "wsm_state_views",
               "wsm_map_pixels", "wsm_gather_palette", "wsm_timing_attach", "wsm_timing_read",
-              "wsm_timing_detach", "wsm_set_graph_replay"):
+              "wsm_timing_detach", "wsm_iterate_graph_create", "wsm_iterate_graph_launch",
+              "wsm_iterate_graph_destroy"):
         getattr(lib, f).restype = I32
     return lib
 
@@ -208,6 +212,11 @@ class State:
         _check(_lib.wsm_iterate_full(ctypes.byref(self.prob), int(max_iters), float(eps),
                                      _stream()), "wsm_iterate_full")
 
+    def graph(self, max_iters: int = 50, eps: float = 1e-4, full: bool = False) -> "IterateGraph":
+        """The launch sequence of iterate(max_iters, eps) (or iterate_full),
+        recorded once into a HIP graph that can be replayed on this state."""
+        return IterateGraph(self, max_iters, eps, full)
+
     def _views(self) -> _Views:
         v = _Views()
         _check(_lib.wsm_state_views(ctypes.byref(self.prob), ctypes.byref(v)), "wsm_state_views")
@@ -221,6 +230,12 @@ class State:
         """float32 [k, 3] palette after the last update (device)."""
         v = self._views()
         return self._slice(v.palette, self.k * 16).view(torch.float32).view(self.k, 4)[:, :3]
+
+    def palette64(self) -> torch.Tensor:
+        """float64 [k, 3] palette after the last update (device): the centers
+        the searches decide by; palette() is their float32 rounding."""
+        v = self._views()
+        return self._slice(v.palette64, self.k * 32).view(torch.float64).view(self.k, 4)[:, :3]
 
     def membership(self) -> torch.Tensor:
         v = self._views()
@@ -239,6 +254,38 @@ class State:
         sse = self._slice(v.sse_history, 8 * HISTORY).view(torch.float64)[:n].cpu().numpy()
         ev = self._slice(v.evals_history, 8 * HISTORY).view(torch.int64)[:n].cpu().numpy()
         return sse, ev
+
+
+class IterateGraph:
+    """A caller-owned HIP graph of one iterate call's launches
+    (wsm_iterate_graph_create / _launch / _destroy).  launch() has the effect
+    of state.iterate(max_iters, eps) (or iterate_full) on the current
+    stream; the state may be re-initialised with init(..., reuse=state)
+    between launches."""
+
+    def __init__(self, state: State, max_iters: int, eps: float, full: bool = False):
+        self.state = state
+        h = ctypes.c_void_p(0)
+        _check(_lib.wsm_iterate_graph_create(ctypes.byref(state.prob), int(max_iters), float(eps),
+                                             1 if full else 0, ctypes.byref(h)),
+               "wsm_iterate_graph_create")
+        self._h = h
+
+    def launch(self) -> None:
+        if not self._h:
+            raise WsmError("graph already closed")
+        _check(_lib.wsm_iterate_graph_launch(self._h, _stream()), "wsm_iterate_graph_launch")
+
+    def close(self) -> None:
+        if self._h:
+            _lib.wsm_iterate_graph_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _new_state(n_points: int, k: int, device) -> torch.Tensor:
@@ -326,12 +373,6 @@ def palette_from_indices(colors: torch.Tensor, indices, out: torch.Tensor | None
 
 KERNELS = dict(reduce_partition=1, reduce_compact=2, rows=3, search=4, map_assign=5,
                map_gather=6, full_step=7)
-
-
-def set_graph_replay(enable: bool) -> bool:
-    """Turn the replay of iteration launch sequences from HIP graphs on or
-    off; returns the previous setting."""
-    return bool(_lib.wsm_set_graph_replay(1 if enable else 0))
 
 
 class kernel_timer:

@@ -28,9 +28,7 @@
 // triple-buffered, so no launch reads what another block of the same launch
 // writes.  A single-block kernel applies the final update after the last
 // step and copies the result to the public slot 0.
-#include <cstring>
-#include <mutex>
-#include <vector>
+#include <new>
 
 #include "sm_block.h"
 
@@ -46,10 +44,12 @@ struct IterArgs {
 };
 
 // Center totals: packed as two u64 (sum cR | sum cG << 32, sum cB | sum c << 32)
-// when 255 * n_pixels < 2^32, else four u64.
+// when 255 * n_pixels < 2^32, else four u64.  The center is the float64
+// quotient of the exact sums (their correctly rounded mean); an empty
+// cluster keeps its center.
 template <bool PACKED>
 __device__ __forceinline__ void totals_to_center(const unsigned long long *T, int c,
-                                                 float4 prev, float4 &out) {
+                                                 double4 prev, double4 &out) {
     unsigned long long sr, sg, sb, w;
     if (PACKED) {
         const unsigned long long a = T[c * 4 + 0], b = T[c * 4 + 1];
@@ -65,40 +65,39 @@ __device__ __forceinline__ void totals_to_center(const unsigned long long *T, in
     }
     if (w != 0ull) {
         const double dw = (double)w;
-        out = make_float4((float)((double)sr / dw), (float)((double)sg / dw),
-                          (float)((double)sb / dw), 0.0f);
+        out = make_double4((double)sr / dw, (double)sg / dw, (double)sb / dw, 0.0);
     } else {
         out = prev;  // empty cluster keeps its center
     }
 }
 
 // Update phase (see the file comment).  Returns the record after the update,
-// identical in every block.  The new centers are in the LDS array cen after
-// the call.
+// identical in every block, with the mode (kMode*) of the new centers.  The
+// new centers are in the LDS array cen after the call, and in float64 in
+// cen64 if it is not null.
 template <int NT, bool PACKED>
-__device__ Record update_phase(const IterArgs &a, int i, float4 *cen, bool writer,
-                               double *dscr, unsigned long long *uscr) {
+__device__ Record update_phase(const IterArgs &a, int i, float4 *cen, double4 *cen64,
+                               bool writer, double *dscr, unsigned long long *uscr) {
     constexpr int kPer = kMaxK / NT > 0 ? kMaxK / NT : 1;
     const int tid = threadIdx.x;
     const Record rin = a.sv.hdr->rec[i & 1];
-    const float4 *pal_in = a.sv.pal + (size_t)(i & 1) * kMaxK;
+    const double4 *pal_in = a.sv.pal64 + (size_t)(i & 1) * kMaxK;
     float4 *pal_out = a.sv.pal + (size_t)((i + 1) & 1) * kMaxK;
+    double4 *pal64_out = a.sv.pal64 + (size_t)((i + 1) & 1) * kMaxK;
     const int prv = (i + 2) % 3;  // totals slot of step i-1
     const unsigned long long *T = a.sv.totals + (size_t)prv * kMaxK * 4;
     // Issue every load first; which values are used is decided afterwards.
     const bool update = (i != 0) && !rin.converged;
-    float4 cv[kPer];
+    double4 cv[kPer];
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
         const int c = tid + r * NT;
-        cv[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        cv[r] = make_double4(0.0, 0.0, 0.0, 0.0);
         if (c < a.k) {
-            const float4 old = pal_in[c];
-            float4 upd;
+            const double4 old = pal_in[c];
+            double4 upd;
             totals_to_center<PACKED>(T, c, old, upd);
-            cv[r].x = update ? upd.x : old.x;
-            cv[r].y = update ? upd.y : old.y;
-            cv[r].z = update ? upd.z : old.z;
+            cv[r] = update ? upd : old;
         }
     }
     // Lane l of the first wave sums partials l, l + 64, l + 128, ... in that
@@ -124,10 +123,15 @@ __device__ Record update_phase(const IterArgs &a, int i, float4 *cen, bool write
             }
         }
     }
+    int flags = 0;
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
         const int c = tid + r * NT;
-        if (c < a.k) cen[c] = cv[r];
+        if (c < a.k) {
+            cen[c] = make_float4((float)cv[r].x, (float)cv[r].y, (float)cv[r].z, 0.0f);
+            if (cen64) cen64[c] = cv[r];
+            flags |= center_flags(cv[r]);
+        }
     }
     Record r = rin;
     if (update) {
@@ -154,9 +158,16 @@ __device__ Record update_phase(const IterArgs &a, int i, float4 *cen, bool write
             a.sv.eval_hist[t - 1] = ev;
         }
     }
-    __syncthreads();
+    r.mode = block_mode(flags);  // barriers that also vote on the mode of the new centers
     if (writer) {
-        for (int c = tid; c < a.k; c += NT) pal_out[c] = cen[c];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int c = tid + q * NT;
+            if (c < a.k) {
+                pal_out[c] = cen[c];
+                pal64_out[c] = cv[q];
+            }
+        }
         if (tid == 0) a.sv.hdr->rec[(i + 1) & 1] = r;
     }
     return r;
@@ -253,19 +264,20 @@ __device__ __forceinline__ void prefetch_points(const IterArgs &a, uint32_t (&ke
 // block's sums into totals slot i % 3 and writes its SSE and evaluation
 // partials.  All threads call it.
 template <bool PACKED, bool DEFER>
-__device__ void finish_block(const IterArgs &a, int i, const float4 *cen, const uint8_t *Ms,
-                             unsigned long long *acc, double *dscr, unsigned long long *uscr,
-                             DeferQueue *dq, double sse, uint32_t ev) {
+__device__ void finish_block(const IterArgs &a, int i, int mode, const float4 *cen,
+                             const double4 *cen64, const uint8_t *Ms, unsigned long long *acc,
+                             double *dscr, unsigned long long *uscr, DeferQueue *dq, double sse,
+                             uint32_t ev) {
     constexpr int NT = kSearchThreads;
     constexpr int NACC = PACKED ? 2 : 4;
     const int tid = threadIdx.x;
     if (DEFER) {
         __syncthreads();
-        finish_deferred<NT>(a.k, cen, Ms, a.sv.rows, dq,
-                            [&](uint32_t idx, uint32_t k, uint32_t c, int best, float bd,
+        finish_deferred<NT>(a.k, mode, cen, cen64, Ms, a.sv.rows, dq,
+                            [&](uint32_t idx, uint32_t k, uint32_t c, int best, double d64,
                                 uint32_t sev) {
             ev += sev;
-            sse += (double)c * (double)bd;
+            sse += (double)c * d64;
             a.sv.m[idx] = (uint8_t)best;
             const unsigned long long cc = c;
             const unsigned long long rr = (k >> 16) & 0xFFu, gg = (k >> 8) & 0xFFu, bb = k & 0xFFu;
@@ -297,14 +309,17 @@ __device__ void finish_block(const IterArgs &a, int i, const float4 *cen, const 
 // Search and accumulation over a block's points (block_slots), in passes of
 // kPass (kCpt points per thread); the first pass's points are already in
 // key/cnt/pm.  Sort-means over the LDS copy Ms of M, or full
-// search for the comparator (Ms unused).  Adds the block's sums into totals
-// slot i % 3 and writes its SSE and evaluation partials.
+// search for the comparator (Ms unused); every choice is then made final in
+// float64 by decide64 (mode: of the centers cen, whose float64 values are
+// cen64), and the SSE is summed from float64 distances.  Adds the block's
+// sums into totals slot i % 3 and writes its SSE and evaluation partials.
 
 template <bool PACKED, bool FULL, bool DEFER>
-__device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const uint8_t *Ms,
-                             unsigned long long *acc, double *dscr, unsigned long long *uscr,
-                             DeferQueue *dq, uint32_t (&key)[kCpt], uint32_t (&cnt)[kCpt],
-                             int (&pm)[kCpt], bool first = false, const float *Dd = nullptr,
+__device__ void search_chunk(const IterArgs &a, int i, int mode, const float4 *cen,
+                             const double4 *cen64, const uint8_t *Ms, unsigned long long *acc,
+                             double *dscr, unsigned long long *uscr, DeferQueue *dq,
+                             uint32_t (&key)[kCpt], uint32_t (&cnt)[kCpt], int (&pm)[kCpt],
+                             bool first = false, const float *Dd = nullptr,
                              FlatScratch *fs = nullptr) {
     constexpr int NT = kSearchThreads;
     constexpr int NW = NT / 64;
@@ -334,30 +349,30 @@ __device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const 
             const bool valid = slot < ns && idx < a.pts.n;
             float x, y, z;
             unpack_key(key[r], x, y, z);
-            float bd = 0.f;
+            float bd = 0.f, s2 = kNoSkip, prev = 0.f, dj = kNoSkip;
             int best = 0;
             bool done = true;
             if (FULL) {
-                if (valid) best = full_scan(x, y, z, pm[r], a.k, cen, bd, ev);
+                if (valid) best = full_scan(x, y, z, pm[r], a.k, cen, bd, s2, ev);
             } else if (first) {
                 // first step (every point starts from center 0, whose whole row
                 // is scanned): the full search gives the same center, and the
                 // scan's evaluation count comes from a binary search of row p
                 if (valid) {
                     uint32_t unused = 0;
-                    best = full_scan(x, y, z, pm[r], a.k, cen, bd, unused);
+                    best = full_scan(x, y, z, pm[r], a.k, cen, bd, s2, unused);
                     ev += sm_scan_evals(x, y, z, pm[r], a.k, cen, Ms, rs);
                 }
             } else if (!DEFER) {
-                if (valid) best = sm_scan(x, y, z, pm[r], a.k, cen, Ms, rs, bd, ev);
+                if (valid) best = sm_scan(x, y, z, pm[r], a.k, cen, Ms, rs, bd, prev, s2, dj, ev);
             } else {
                 // the wave's scans over the row heads together; a scan that
                 // goes past the head is deferred (or, with the queue full,
                 // carried on by its lane)
                 float thr;
                 bool more;
-                sm_scan_flat(valid, key[r], pm[r], a.k, cen, Ms, Dd, fs[wave], thr, bd, best, ev,
-                             more);
+                sm_scan_flat(valid, key[r], pm[r], a.k, cen, Ms, Dd, fs[wave], thr, prev, bd, s2,
+                             dj, best, ev, more);
                 if (more) {
                     const uint32_t q = atomicAdd(&dq->n, 1u);
                     if (q < (uint32_t)kDeferCap) {
@@ -365,6 +380,7 @@ __device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const 
                         dq->key[q] = key[r];
                         dq->cnt[q] = cnt[r];
                         dq->bd[q] = __float_as_uint(bd);
+                        dq->s2[q] = __float_as_uint(s2);
                         dq->pjb[q] = ((uint32_t)kRowPrefix << 16) | ((uint32_t)pm[r] << 8) |
                                      (uint32_t)best;
                         done = false;
@@ -372,18 +388,23 @@ __device__ void search_chunk(const IterArgs &a, int i, const float4 *cen, const 
                         const RowView rv{Ms + pm[r] * rs, a.sv.rows + (size_t)pm[r] * kRowStride,
                                          kRowPrefix};
                         int j = kRowPrefix;
-                        sm_scan_range(x, y, z, pm[r], a.k, cen, rv, thr, j, a.k, bd, best, ev);
+                        dj = kNoSkip;
+                        sm_scan_range(x, y, z, pm[r], a.k, cen, rv, thr, j, a.k, bd, best, s2, dj,
+                                      ev);
                     }
                 }
             }
-            if (valid && done) {
+            const bool fin = valid && done;
+            const double d64 = decide64(fin, key[r], pm[r], a.k, mode, cen64, best, bd, s2, prev,
+                                        dj);
+            if (fin) {
                 a.sv.m[idx] = (uint8_t)best;
-                sse += (double)cnt[r] * (double)bd;
+                sse += (double)cnt[r] * d64;
             }
-            accumulate<PACKED>(acc, best, valid && done, key[r], cnt[r]);
+            accumulate<PACKED>(acc, best, fin, key[r], cnt[r]);
         }
     }
-    finish_block<PACKED, DEFER>(a, i, cen, Ms, acc, dscr, uscr, dq, sse, ev);
+    finish_block<PACKED, DEFER>(a, i, mode, cen, cen64, Ms, acc, dscr, uscr, dq, sse, ev);
 }
 
 // Sort-means step i, first launch: the update of step i-1 in every block
@@ -397,7 +418,7 @@ __global__ __launch_bounds__(kSortThreads) void rows_kernel(IterArgs a, int i) {
     __shared__ double dscr[kSortThreads / 64];
     __shared__ unsigned long long uscr[kSortThreads / 64];
     const int p = blockIdx.x;
-    const Record rec = update_phase<kSortThreads, PACKED>(a, i, cen, p == 0, dscr, uscr);
+    const Record rec = update_phase<kSortThreads, PACKED>(a, i, cen, nullptr, p == 0, dscr, uscr);
     if (rec.converged) return;
     if (p == 0) {
         unsigned long long *T = a.sv.totals + (size_t)(i % 3) * kMaxK * 4;
@@ -412,6 +433,7 @@ __global__ __launch_bounds__(kSortThreads) void rows_kernel(IterArgs a, int i) {
 template <bool PACKED, bool DEFER, bool FIRST>
 __global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int i) {
     __shared__ float4 cen[kMaxK];
+    __shared__ double4 cen64[kMaxK];
     __shared__ unsigned long long acc[kMaxK * 4];
     // rows of M: the first kRowPrefix entries when scans defer, else whole
     __shared__ __align__(16) uint8_t Ms[kMaxK * (DEFER ? kRowPrefix : kRowStride)];
@@ -431,6 +453,8 @@ __global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int 
     // the loads overlap (they are only used if the loop has not stopped).
     const float4 *pal = a.sv.pal + (size_t)((i + 1) & 1) * kMaxK;
     const float4 pc = tid < a.k ? pal[tid] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const double4 *pal64 = a.sv.pal64 + (size_t)((i + 1) & 1) * kMaxK;
+    const double4 pc64 = tid < a.k ? pal64[tid] : make_double4(0.0, 0.0, 0.0, 0.0);
     RowRegs<NT> R;
     fetch_rows<NT, DEFER>(a.sv.rows, a.k, R);
     constexpr int kDdRegs = DEFER ? kMaxK * kRowDist / 4 / NT : 1;  // 16-byte pieces per thread
@@ -446,7 +470,10 @@ __global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int 
     }
     const Record rec = a.sv.hdr->rec[(i + 1) & 1];
     if (rec.converged) return;
-    if (tid < a.k) cen[tid] = pc;
+    if (tid < a.k) {
+        cen[tid] = pc;
+        cen64[tid] = pc64;
+    }
     store_rows<NT, DEFER>(R, a.k, Ms);
     if (DEFER) {
 #pragma unroll
@@ -461,8 +488,8 @@ __global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int 
     // The launch for a call's first step (FIRST) checks whether the state has
     // completed no step yet, i.e. every membership is still 0 (state init).
     const bool first = FIRST && rec.iters == 0;
-    search_chunk<PACKED, false, DEFER>(a, i, cen, Ms, acc, dscr, uscr, &dq, key, cnt, pm, first,
-                                       Dd, fs);
+    search_chunk<PACKED, false, DEFER>(a, i, rec.mode, cen, cen64, Ms, acc, dscr, uscr, &dq, key,
+                                       cnt, pm, first, Dd, fs);
 }
 
 // Rows of M for palette slot 0 of the state (the pixel map's palette).
@@ -482,6 +509,7 @@ __global__ __launch_bounds__(kSortThreads) void palette_rows_kernel(StateView sv
 template <bool PACKED>
 __global__ __launch_bounds__(kSearchThreads) void fused_step_kernel(IterArgs a, int i) {
     __shared__ float4 cen[kMaxK];
+    __shared__ double4 cen64[kMaxK];
     __shared__ unsigned long long acc[kMaxK * 4];
     __shared__ __align__(16) unsigned long long keys[kFusedMaxK * kFusedMaxK];
     __shared__ __align__(16) uint8_t Ms[kFusedMaxK * kFusedMaxK];
@@ -495,7 +523,7 @@ __global__ __launch_bounds__(kSearchThreads) void fused_step_kernel(IterArgs a, 
     uint32_t key[kCpt], cnt[kCpt];
     int pm[kCpt];
     prefetch_points(a, key, cnt, pm);
-    const Record rec = update_phase<NT, PACKED>(a, i, cen, blockIdx.x == 0, dscr, uscr);
+    const Record rec = update_phase<NT, PACKED>(a, i, cen, cen64, blockIdx.x == 0, dscr, uscr);
     if (rec.converged) return;
     if (blockIdx.x == 0) {
         unsigned long long *Tn = a.sv.totals + (size_t)((i + 1) % 3) * kMaxK * 4;
@@ -523,7 +551,8 @@ __global__ __launch_bounds__(kSearchThreads) void fused_step_kernel(IterArgs a, 
         Ms[p * lds_row_stride(K) + r] = (uint8_t)t;
     }
     __syncthreads();
-    search_chunk<PACKED, false, false>(a, i, cen, Ms, acc, dscr, uscr, nullptr, key, cnt, pm);
+    search_chunk<PACKED, false, false>(a, i, rec.mode, cen, cen64, Ms, acc, dscr, uscr, nullptr,
+                                       key, cnt, pm);
 }
 
 // Full-search comparator: one launch per step, the update applied
@@ -531,6 +560,7 @@ __global__ __launch_bounds__(kSearchThreads) void fused_step_kernel(IterArgs a, 
 template <bool PACKED>
 __global__ __launch_bounds__(kSearchThreads) void full_step_kernel(IterArgs a, int i) {
     __shared__ float4 cen[kMaxK];
+    __shared__ double4 cen64[kMaxK];
     __shared__ unsigned long long acc[kMaxK * 4];
     __shared__ double dscr[kSearchThreads / 64];
     __shared__ unsigned long long uscr[kSearchThreads / 64];
@@ -540,7 +570,7 @@ __global__ __launch_bounds__(kSearchThreads) void full_step_kernel(IterArgs a, i
     uint32_t key[kCpt], cnt[kCpt];
     int pm[kCpt];
     prefetch_points(a, key, cnt, pm);
-    const Record rec = update_phase<NT, PACKED>(a, i, cen, blockIdx.x == 0, dscr, uscr);
+    const Record rec = update_phase<NT, PACKED>(a, i, cen, cen64, blockIdx.x == 0, dscr, uscr);
     if (rec.converged) return;
     if (blockIdx.x == 0) {
         unsigned long long *Tn = a.sv.totals + (size_t)((i + 1) % 3) * kMaxK * 4;
@@ -548,7 +578,8 @@ __global__ __launch_bounds__(kSearchThreads) void full_step_kernel(IterArgs a, i
     }
     for (int c = tid; c < a.k * NACC; c += NT) acc[c] = 0ull;
     __syncthreads();
-    search_chunk<PACKED, true, false>(a, i, cen, nullptr, acc, dscr, uscr, nullptr, key, cnt, pm);
+    search_chunk<PACKED, true, false>(a, i, rec.mode, cen, cen64, nullptr, acc, dscr, uscr,
+                                      nullptr, key, cnt, pm);
 }
 
 // Final update after the last step of a call (one block).  Publishes the
@@ -556,12 +587,16 @@ __global__ __launch_bounds__(kSearchThreads) void full_step_kernel(IterArgs a, i
 template <bool PACKED>
 __global__ __launch_bounds__(kRowThreads) void final_kernel(IterArgs a, int i) {
     __shared__ float4 cen[kMaxK];
+    __shared__ double4 cen64[kMaxK];
     __shared__ double dscr[4];
     __shared__ unsigned long long uscr[4];
     const int tid = threadIdx.x;
-    const Record r = update_phase<kRowThreads, PACKED>(a, i, cen, true, dscr, uscr);
+    const Record r = update_phase<kRowThreads, PACKED>(a, i, cen, cen64, true, dscr, uscr);
     __syncthreads();
-    for (int c = tid; c < a.k; c += kRowThreads) a.sv.pal[c] = cen[c];
+    for (int c = tid; c < a.k; c += kRowThreads) {
+        a.sv.pal[c] = cen[c];
+        a.sv.pal64[c] = cen64[c];
+    }
     unsigned long long *T0 = a.sv.totals;
     for (int c = tid; c < kMaxK * 4; c += kRowThreads) T0[c] = 0ull;
     if (tid == 0) {
@@ -593,7 +628,7 @@ __global__ void init_state_kernel(StateView sv, int k, int points, int grid,
         z.iters = 0;
         z.converged = 0;
         z.err = 0;
-        z.pad = 0;
+        z.mode = kModeResolve;
         z.sse_last = 0.0;
         z.pad2 = 0.0;
         h->rec[0] = z;
@@ -601,10 +636,12 @@ __global__ void init_state_kernel(StateView sv, int k, int points, int grid,
         for (int j = 0; j < 4; ++j) h->info[j] = 0;
     }
     for (int64_t c = gt; c < 2 * kMaxK; c += stride) {
+        const int64_t j = c % kMaxK;  // both slots hold the initial palette
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (c < k) v = make_float4(init_palette[3 * c], init_palette[3 * c + 1],
-                                   init_palette[3 * c + 2], 0.f);
+        if (j < k) v = make_float4(init_palette[3 * j], init_palette[3 * j + 1],
+                                   init_palette[3 * j + 2], 0.f);
         sv.pal[c] = v;
+        sv.pal64[c] = make_double4((double)v.x, (double)v.y, (double)v.z, 0.0);
     }
     for (int64_t c = gt; c < 3 * kMaxK * 4; c += stride) sv.totals[c] = 0ull;
     for (int64_t c = gt; c < 2 * kMaxGrid; c += stride) {
@@ -794,118 +831,73 @@ static int launch_direct(const IterArgs &a, int max_iters, bool full, bool packe
                   : launch_steps<false>(a, max_iters, full, stream);
 }
 
-// ---------------------------------------------------------------------------
-// Replay of a call's launch sequence from a HIP graph.  A sequence depends
-// only on the call's arguments.  The first call with a set of arguments
-// launches directly and remembers them; the second records the sequence
-// (on a stream of the library's own) and every later one replays it on the
-// caller's stream, so one-off calls never pay for the recording.  Graphs
-// are kept until the process ends; past kMaxGraphs distinct argument sets,
-// calls launch directly.
-namespace {
-
-struct GraphEntry {
-    int device;
-    const void *state;
-    const uint32_t *colors, *counts;
-    const uint8_t *rgb;
-    int64_t n, n_pixels;
-    int is_pixels, k, grid, max_iters, full, packed;
-    uint64_t eps_bits;
-    hipGraphExec_t exec;
-};
-
-constexpr size_t kMaxGraphs = 64;
-constexpr int kMaxDevices = 64;
-std::mutex g_graph_mu;
-std::vector<GraphEntry> g_graphs;
-hipStream_t g_capture_stream[kMaxDevices] = {};
-int g_graph_replay = 1;
-
-bool same_call(const GraphEntry &e, const GraphEntry &q) {
-    return e.device == q.device && e.state == q.state && e.colors == q.colors &&
-           e.counts == q.counts && e.rgb == q.rgb && e.n == q.n && e.n_pixels == q.n_pixels &&
-           e.is_pixels == q.is_pixels && e.k == q.k && e.grid == q.grid &&
-           e.max_iters == q.max_iters && e.full == q.full && e.packed == q.packed &&
-           e.eps_bits == q.eps_bits;
-}
-
-}  // namespace
-
-static int launch_replayed(const IterArgs &a, int max_iters, bool full, bool packed,
-                           hipStream_t stream) {
-    GraphEntry q{};
-    if (hipGetDevice(&q.device) != hipSuccess || q.device < 0 || q.device >= kMaxDevices)
-        return launch_direct(a, max_iters, full, packed, stream);
-    q.state = a.sv.hdr;
-    q.colors = a.pts.colors;
-    q.counts = a.pts.counts;
-    q.rgb = a.pts.rgb;
-    q.n = a.pts.n;
-    q.n_pixels = a.n_pixels;
-    q.is_pixels = a.pts.is_pixels;
-    q.k = a.k;
-    q.grid = a.grid;
-    q.max_iters = max_iters;
-    q.full = full ? 1 : 0;
-    q.packed = packed ? 1 : 0;
-    std::memcpy(&q.eps_bits, &a.eps, sizeof(q.eps_bits));
-    std::lock_guard<std::mutex> lock(g_graph_mu);
-    GraphEntry *hit = nullptr;
-    for (GraphEntry &e : g_graphs)
-        if (same_call(e, q)) hit = &e;
-    if (!hit) {
-        // first sighting: remember the arguments, launch directly
-        if (g_graphs.size() < kMaxGraphs) {
-            q.exec = nullptr;
-            g_graphs.push_back(q);
-        }
-        return launch_direct(a, max_iters, full, packed, stream);
-    }
-    hipGraphExec_t exec = hit->exec;
-    if (!exec) {
-        hipStream_t &cs = g_capture_stream[q.device];
-        if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
-            cs = nullptr;
-            return WSM_EHIP;
-        }
-        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
-            return WSM_EHIP;
-        const int rc = launch_direct(a, max_iters, full, packed, cs);
-        hipGraph_t graph = nullptr;
-        const hipError_t end = hipStreamEndCapture(cs, &graph);
-        if (rc != WSM_OK || end != hipSuccess || !graph) {
-            if (graph) (void)hipGraphDestroy(graph);
-            (void)hipGetLastError();
-            return WSM_EHIP;
-        }
-        const hipError_t inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (inst != hipSuccess) return WSM_EHIP;
-        hit->exec = exec;
-    }
-    return hipGraphLaunch(exec, stream) == hipSuccess ? WSM_OK : WSM_EHIP;
-}
-
 static int iterate_impl(const wsm_problem *prob, int max_iters, double eps, bool full,
                         hipStream_t stream) {
     int rc = check_iter_args(prob, max_iters, eps);
     if (rc != WSM_OK) return rc;
     const IterArgs a = make_args(prob, eps);
-    const bool packed = packed_sums(prob);
     (void)hipGetLastError();
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return WSM_EHIP;
-    if (g_graph_replay && cap == hipStreamCaptureStatusNone && !timing_attached())
-        return launch_replayed(a, max_iters, full, packed, stream);
-    return launch_direct(a, max_iters, full, packed, stream);
+    return launch_direct(a, max_iters, full, packed_sums(prob), stream);
 }
 
-extern "C" int wsm_set_graph_replay(int enable) {
-    std::lock_guard<std::mutex> lock(g_graph_mu);
-    const int prev = g_graph_replay;
-    g_graph_replay = enable ? 1 : 0;
-    return prev;
+// ---------------------------------------------------------------------------
+// A caller-owned HIP graph of one call's launch sequence.  The sequence
+// depends only on the call's arguments, so it is recorded once (on a stream
+// the create call makes and destroys) and replayed by every launch.
+struct wsm_graph {
+    uint32_t magic;
+    hipGraphExec_t exec;
+};
+
+constexpr uint32_t kGraphMagic = 0x574D4752u;
+
+extern "C" int wsm_iterate_graph_create(const wsm_problem *prob, int max_iters, double eps,
+                                        int full, wsm_graph **graph) {
+    if (!graph) return WSM_EINVAL;
+    *graph = nullptr;
+    int rc = check_iter_args(prob, max_iters, eps);
+    if (rc != WSM_OK) return rc;
+    const IterArgs a = make_args(prob, eps);
+    (void)hipGetLastError();
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return WSM_EHIP;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+    rc = WSM_EHIP;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        const int lrc = launch_direct(a, max_iters, full != 0, packed_sums(prob), cs);
+        const hipError_t end = hipStreamEndCapture(cs, &g);
+        if (lrc == WSM_OK && end == hipSuccess && g &&
+            hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess)
+            rc = WSM_OK;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    (void)hipGetLastError();
+    if (rc != WSM_OK) return rc;
+    wsm_graph *h = new (std::nothrow) wsm_graph;
+    if (!h) {
+        (void)hipGraphExecDestroy(exec);
+        return WSM_EHIP;
+    }
+    h->magic = kGraphMagic;
+    h->exec = exec;
+    *graph = h;
+    return WSM_OK;
+}
+
+extern "C" int wsm_iterate_graph_launch(wsm_graph *graph, hipStream_t stream) {
+    if (!graph || graph->magic != kGraphMagic) return WSM_EINVAL;
+    return hipGraphLaunch(graph->exec, stream) == hipSuccess ? WSM_OK : WSM_EHIP;
+}
+
+extern "C" int wsm_iterate_graph_destroy(wsm_graph *graph) {
+    if (!graph) return WSM_OK;
+    if (graph->magic != kGraphMagic) return WSM_EINVAL;
+    const hipError_t e = hipGraphExecDestroy(graph->exec);
+    graph->magic = 0u;
+    delete graph;
+    return e == hipSuccess ? WSM_OK : WSM_EHIP;
 }
 
 extern "C" int wsm_iterate(const wsm_problem *prob, int max_iters, double eps,
@@ -924,6 +916,7 @@ extern "C" int wsm_state_views(const wsm_problem *prob, wsm_views *views) {
     if (rc != WSM_OK) return rc;
     const StateView sv = make_view(prob->state);
     views->palette = (const float *)sv.pal;
+    views->palette64 = (const double *)sv.pal64;
     views->membership = sv.m;
     views->sse_history = sv.sse_hist;
     views->evals_history = (const int64_t *)sv.eval_hist;

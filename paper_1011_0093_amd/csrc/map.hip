@@ -7,9 +7,11 @@
 //           search for large K (sm_block.h): the row heads of M and their
 //           distances in LDS, a wave's scans over them spread over its lanes,
 //           the rare longer ones finished by whole waves.  One block per CU.
-//           The palette index is scattered into a 2^24-entry
-//           byte table laid out in 4 x 4 x 4 color cells (lut_index);
-//           count * distance is summed per block for the MSE.
+//           Each choice is made final in float64 against the float64
+//           palette (decide64), and the palette index is scattered into a
+//           2^24-entry byte table laid out in 4 x 4 x 4 color cells
+//           (lut_index); count * float64 distance is summed per block for
+//           the MSE.
 //   gather  16 pixels per lane: three 16-byte loads, 16 table lookups, one
 //           16-byte store of indices (and 48 bytes of rounded palette colors
 //           when asked for).  Block 0 also sums the MSE partials.
@@ -45,6 +47,7 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
     constexpr int NT = kSearchThreads;
     constexpr int NW = NT / 64;
     __shared__ float4 cen[kMaxK];
+    __shared__ double4 cen64[kMaxK];
     // rows of M: their heads (FLAT) or whole
     __shared__ __align__(16) uint8_t Ms[kMaxK * (FLAT ? kRowPrefix : kRowStride)];
     __shared__ __align__(16) float Dd[FLAT ? kMaxK * kRowDist : 4];  // the heads' distances
@@ -59,7 +62,13 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
     const int64_t grid = gridDim.x;
     const int64_t chunks = (n + 63) / 64;
     const int64_t ns = chunks > (int64_t)blockIdx.x ? (chunks - blockIdx.x + grid - 1) / grid : 0;
-    for (int c = tid; c < K; c += NT) cen[c] = sv.pal[c];
+    int flags = 0;
+    for (int c = tid; c < K; c += NT) {
+        const double4 c64 = sv.pal64[c];
+        cen[c] = sv.pal[c];
+        cen64[c] = c64;
+        flags |= center_flags(c64);
+    }
     RowRegs<NT> R;
     fetch_rows<NT, FLAT>(sv.rows, K, R);
     store_rows<NT, FLAT>(R, K, Ms);
@@ -67,7 +76,7 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
         for (int q = tid; q < K * (kRowDist / 4); q += NT)
             ((uint4 *)Dd)[q] = ((const uint4 *)sv.rowd)[q];
     if (tid == 0) dq.n = 0u;
-    __syncthreads();
+    const int mode = block_mode(flags);
     double acc = 0.0;
     uint32_t ev = 0;
     for (int64_t s0 = 0; s0 < ns; s0 += kCpt * NW) {
@@ -95,16 +104,17 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
             // the wave's scans over the row heads together; one that goes
             // past the head is deferred (or, with the queue full, carried on
             // by its lane)
-            float thr = 0.f, bd = 0.f;
+            float thr = 0.f, bd = 0.f, s2 = kNoSkip, prev = 0.f, dj = kNoSkip;
             int best = 0;
             bool more = false;
             if (FLAT) {
-                sm_scan_flat(valid, key[r], pm[r], K, cen, Ms, Dd, fs[wave], thr, bd, best, ev,
-                             more);
+                sm_scan_flat(valid, key[r], pm[r], K, cen, Ms, Dd, fs[wave], thr, prev, bd, s2, dj,
+                             best, ev, more);
             } else if (valid) {
                 float x, y, z;
                 unpack_key(key[r], x, y, z);
-                best = sm_scan(x, y, z, pm[r], K, cen, Ms, lds_row_stride(K), bd, ev);
+                best = sm_scan(x, y, z, pm[r], K, cen, Ms, lds_row_stride(K), bd, prev, s2, dj,
+                               ev);
             }
             bool done = true;
             if (FLAT && more) {
@@ -114,6 +124,7 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
                     dq.key[q] = key[r];
                     dq.cnt[q] = cnt[r];
                     dq.bd[q] = __float_as_uint(bd);
+                    dq.s2[q] = __float_as_uint(s2);
                     dq.pjb[q] = ((uint32_t)kRowPrefix << 16) | ((uint32_t)pm[r] << 8) |
                                 (uint32_t)best;
                     done = false;
@@ -123,21 +134,24 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
                     const RowView rv{Ms + pm[r] * kRowPrefix, sv.rows + (size_t)pm[r] * kRowStride,
                                      kRowPrefix};
                     int j = kRowPrefix;
-                    sm_scan_range(x, y, z, pm[r], K, cen, rv, thr, j, K, bd, best, ev);
+                    dj = kNoSkip;
+                    sm_scan_range(x, y, z, pm[r], K, cen, rv, thr, j, K, bd, best, s2, dj, ev);
                 }
             }
-            if (valid && done) {
+            const bool fin = valid && done;
+            const double d64 = decide64(fin, key[r], pm[r], K, mode, cen64, best, bd, s2, prev, dj);
+            if (fin) {
                 lut[lut_index_key(key[r])] = (uint8_t)best;
-                acc += (double)cnt[r] * (double)bd;
+                acc += (double)cnt[r] * d64;
             }
         }
     }
     if (FLAT) {
         __syncthreads();
-        finish_deferred<NT>(K, cen, Ms, sv.rows, &dq,
-                            [&](uint32_t, uint32_t k, uint32_t c, int best, float bd, uint32_t) {
+        finish_deferred<NT>(K, mode, cen, cen64, Ms, sv.rows, &dq,
+                            [&](uint32_t, uint32_t k, uint32_t c, int best, double d64, uint32_t) {
             lut[lut_index_key(k)] = (uint8_t)best;
-            acc += (double)c * (double)bd;
+            acc += (double)c * d64;
         });
     }
     const double s = block_sum_f64<NT>(acc, dscr);
@@ -148,17 +162,18 @@ template <bool VEC>
 __global__ __launch_bounds__(kMapThreads) void map_gather_kernel(
     const uint8_t *__restrict__ rgb, int64_t n, const uint8_t *__restrict__ lut,
     uint8_t *__restrict__ index_out, uint8_t *__restrict__ rgb_out, double *__restrict__ mse_out,
-    const double *__restrict__ map_part, int nparts, const float4 *__restrict__ pal, int K) {
+    const double *__restrict__ map_part, int nparts, const double4 *__restrict__ pal, int K) {
     __shared__ uint32_t rpal[kMaxK];  // rounded palette colors, packed 0x00RRGGBB
     const int tid = threadIdx.x;
     if (rgb_out) {
         for (int c = tid; c < kMaxK; c += kMapThreads) {
             uint32_t v = 0u;
             if (c < K) {
-                const float4 q = pal[c];
-                const float r = fminf(fmaxf(rintf(q.x), 0.f), 255.f);
-                const float g = fminf(fmaxf(rintf(q.y), 0.f), 255.f);
-                const float b = fminf(fmaxf(rintf(q.z), 0.f), 255.f);
+                // the float64 palette rounded half to even, clamped to 0..255
+                const double4 q = pal[c];
+                const double r = fmin(fmax(rint(q.x), 0.0), 255.0);
+                const double g = fmin(fmax(rint(q.y), 0.0), 255.0);
+                const double b = fmin(fmax(rint(q.z), 0.0), 255.0);
                 v = ((uint32_t)r << 16) | ((uint32_t)g << 8) | (uint32_t)b;
             }
             rpal[c] = v;
@@ -252,12 +267,12 @@ extern "C" int wsm_map_pixels(const wsm_problem *prob, const uint8_t *rgb, int64
     if (vec)
         WSM_LAUNCH(WSM_KERNEL_MAP_GATHER, map_gather_kernel<true>, dim3((unsigned)gb),
                    dim3(kMapThreads), stream, rgb, n_pixels, (const uint8_t *)lut, index_out,
-                   rgb_out, mse_out, (const double *)sv.map_part, (int)nb, (const float4 *)sv.pal,
+                   rgb_out, mse_out, (const double *)sv.map_part, (int)nb, (const double4 *)sv.pal64,
                    prob->k);
     else
         WSM_LAUNCH(WSM_KERNEL_MAP_GATHER, map_gather_kernel<false>, dim3((unsigned)gb),
                    dim3(kMapThreads), stream, rgb, n_pixels, (const uint8_t *)lut, index_out,
-                   rgb_out, mse_out, (const double *)sv.map_part, (int)nb, (const float4 *)sv.pal,
+                   rgb_out, mse_out, (const double *)sv.map_part, (int)nb, (const double4 *)sv.pal64,
                    prob->k);
     if (hipGetLastError() != hipSuccess) return WSM_EHIP;
     return WSM_OK;

@@ -193,11 +193,13 @@ struct RowView {
 // discarded) and returns whether the scan has ended (stop found or row
 // exhausted); j is left at the next batch.  Reads past the row's K - 1
 // entries stay inside the row (its strides are multiples of 16) and the
-// center table.
+// center table.  s2 tracks the second smallest evaluated distance (the
+// previous center's included); dj is set to d(c_p, c_t)^2 of the entry the
+// scan stops at (left alone when the row runs out).
 __device__ __forceinline__ bool sm_scan_range(float x, float y, float z, int p, int K,
                                               const float4 *cen, const RowView &row, float thr,
                                               int &j, int j_end, float &bd, int &best,
-                                              uint32_t &ev) {
+                                              float &s2, float &dj, uint32_t &ev) {
     const float4 cp = cen[p];
     const int n = K - 1;
     const int jm = j_end < n ? j_end : n;
@@ -219,8 +221,10 @@ __device__ __forceinline__ bool sm_scan_range(float x, float y, float z, int p, 
             if (!stop) {
                 if (j + e >= n || dpt[e] >= thr) {
                     stop = true;
+                    if (j + e < n) dj = dpt[e];
                 } else {
                     ev += 1;
+                    s2 = fminf(s2, fmaxf(d[e], bd));
                     if (better_center(d[e], bd, t[e], best, p)) {
                         bd = d[e];
                         best = t[e];
@@ -235,13 +239,18 @@ __device__ __forceinline__ bool sm_scan_range(float x, float y, float z, int p, 
 
 // The whole scan of one point over its row in LDS, in one loop: the start
 // at the previous center, then the row in batches as in sm_scan_range.
+// Besides the choice and its distance it returns what certified() needs:
+// the previous center's distance, the second smallest evaluated distance and
+// the first skipped entry's center distance (kNoSkip if none was skipped).
 __device__ __forceinline__ int sm_scan(float x, float y, float z, int p, int K,
                                        const float4 *cen, const uint8_t *Ms, int rs,
-                                       float &best_d, uint32_t &ev) {
+                                       float &best_d, float &prev_out, float &s2_out,
+                                       float &dj_out, uint32_t &ev) {
     const float4 cp = cen[p];
     const float prev = sq_dist(x, y, z, cp.x, cp.y, cp.z);
     const float thr = prev * kBreakScale;
     float bd = prev;
+    float s2 = kNoSkip, dj = kNoSkip;
     int best = p;
     ev += 1;
     const uint8_t *row = Ms + p * rs;
@@ -263,8 +272,10 @@ __device__ __forceinline__ int sm_scan(float x, float y, float z, int p, int K,
             if (!stop) {
                 if (j + e >= n || dpt[e] >= thr) {
                     stop = true;
+                    if (j + e < n) dj = dpt[e];
                 } else {
                     ev += 1;
+                    s2 = fminf(s2, fmaxf(d[e], bd));
                     if (better_center(d[e], bd, t[e], best, p)) {
                         bd = d[e];
                         best = t[e];
@@ -275,6 +286,9 @@ __device__ __forceinline__ int sm_scan(float x, float y, float z, int p, int K,
         if (stop) break;
     }
     best_d = bd;
+    prev_out = prev;
+    s2_out = s2;
+    dj_out = dj;
     return best;
 }
 
@@ -289,17 +303,21 @@ __device__ __forceinline__ unsigned long long scan_key(float d, int t, int p) {
 // the threshold, and the entries before it are reduced with scan_key.  Every
 // argument but t_first is the same in all lanes, and all 64 lanes must call
 // it; t_first is row entry j + lane, loaded by the caller (any value where
-// j + lane >= K - 1).  The results (bd, best, evaluations made) are the same
-// in all lanes.
+// j + lane >= K - 1).  The results (bd, best, the second smallest evaluated
+// distance s2, the stop entry's center distance dj -- kNoSkip if the row
+// runs out -- and the evaluations made) are the same in all lanes.
 __device__ __forceinline__ void sm_finish_wave(float x, float y, float z, int p, int K,
                                                const float4 *cen, const RowView &row, float thr,
                                                int j, int t_first, float &bd, int &best,
-                                               uint32_t &evals) {
+                                               float &s2, float &dj, uint32_t &evals) {
     const int lane = threadIdx.x & 63;
     const int n = K - 1;
     const float4 cp = cen[p];
     unsigned long long bk = scan_key(bd, best, p);
+    // second smallest so far; only its distance is used
+    unsigned long long bk2 = s2 < kNoSkip ? ((unsigned long long)__float_as_uint(s2) << 32) : ~0ull;
     uint32_t sev = 0;
+    dj = kNoSkip;
     for (int jb = j; jb < n; jb += 64) {
         const int jj = jb + lane;
         const bool in = jj < n;
@@ -311,12 +329,22 @@ __device__ __forceinline__ void sm_finish_wave(float x, float y, float z, int p,
         const int first = smask != 0ull ? __builtin_ctzll(smask) : 64;
         const bool ok = lane < first;
         sev += (uint32_t)__popcll(__ballot(ok));
-        const unsigned long long k = wave_last_u64(wave_min_u64(ok ? scan_key(d, t, p) : ~0ull));
-        bk = k < bk ? k : bk;
-        if (first < 64) break;
+        const unsigned long long kl = ok ? scan_key(d, t, p) : ~0ull;
+        const unsigned long long m1 = wave_last_u64(wave_min_u64(kl));
+        const unsigned long long m2 = wave_last_u64(wave_min_u64(kl == m1 ? ~0ull : kl));
+        const unsigned long long hi = bk > m1 ? bk : m1;
+        bk = bk < m1 ? bk : m1;
+        bk2 = bk2 < hi ? bk2 : hi;
+        bk2 = bk2 < m2 ? bk2 : m2;
+        if (first < 64) {
+            const float dstop = __shfl(dpt, first, 64);
+            if (jb + first < n) dj = dstop;
+            break;
+        }
     }
     bd = __uint_as_float((uint32_t)(bk >> 32));
     best = (bk & 0x100ull) ? (int)(bk & 0xFFull) : p;
+    s2 = bk2 == ~0ull ? kNoSkip : __uint_as_float((uint32_t)(bk2 >> 32));
     evals = sev;
 }
 
@@ -325,6 +353,7 @@ struct FlatScratch {
     float4 pt[64];               // lane l: the point (x, y, z) and, as int bits, the
                                  // offset of its pair q's row entry: p * kRowPrefix - first pair
     unsigned long long bk[64];   // lane l: smallest scan_key so far
+    unsigned long long bk2[64];  // lane l: second smallest scan_key so far
     __align__(16) uint8_t head[64 * kRowPrefix];  // pair q: 1 + the lane whose pairs start at q
 };
 
@@ -343,14 +372,20 @@ struct FlatScratch {
 // other than the previous one).
 //   The result is the sequential scan's: bd, best, evaluations 1 + n, and
 // `more` when the break lies past entry L - 1 and the row goes on (the scan
-// then continues from entry L with threshold thr).  Ms holds rows of
-// kRowPrefix entries.  All 64 lanes call it.  Lanes of one wave exchange
-// data through LDS here; LDS operations of a wave take effect in issue
-// order, and signal fences keep the compiler from reordering them.
+// then continues from entry L with threshold thr).  It also returns the
+// previous center's distance, the second smallest evaluated distance s2
+// (each pair's key goes into the point's minimum, and whichever of the two
+// loses goes into its second minimum: every key but the final minimum ends
+// there) and the center distance dj of the stop entry (kNoSkip if the row
+// runs out; unset with `more`).  Ms holds rows of kRowPrefix entries.  All
+// 64 lanes call it.  Lanes of one wave exchange data through LDS here; LDS
+// operations of a wave take effect in issue order, and signal fences keep
+// the compiler from reordering them.
 __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, int K,
                                              const float4 *cen, const uint8_t *Ms,
                                              const float *Dd, FlatScratch &fs, float &thr,
-                                             float &bd, int &best, uint32_t &ev, bool &more) {
+                                             float &prev_out, float &bd, float &s2, float &dj,
+                                             int &best, uint32_t &ev, bool &more) {
     const int lane = threadIdx.x & 63;
     const int L = K - 1 < kRowPrefix ? K - 1 : kRowPrefix;
     const int pp = valid ? p : 0;
@@ -366,6 +401,8 @@ __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, in
         if (n + step <= L && dr[n + step - 1] < thr) n += step;
     if (!valid) n = 0;
     more = valid && n == L && L < K - 1;
+    dj = n < L ? dr[n] : kNoSkip;
+    prev_out = prev;
     const uint32_t incl = wave_incl_sum((uint32_t)n);
     const int excl = (int)incl - n;
     const int total = (int)wave_last_u32(incl);
@@ -375,6 +412,7 @@ __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, in
     h4[lane + 64] = make_uint4(0u, 0u, 0u, 0u);
     fs.pt[lane] = make_float4(x, y, z, __int_as_float(pp * kRowPrefix - excl));
     fs.bk[lane] = scan_key(prev, pp, pp);
+    fs.bk2[lane] = ~0ull;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if (n > 0) fs.head[excl] = (uint8_t)(lane + 1);
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -390,14 +428,89 @@ __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, in
             const float4 po = fs.pt[o];
             const int t = Ms[__float_as_int(po.w) + q];
             const float4 ct = cen[t];
-            atomicMin(&fs.bk[o], scan_key(sq_dist(po.x, po.y, po.z, ct.x, ct.y, ct.z), t, -1));
+            const unsigned long long kq =
+                scan_key(sq_dist(po.x, po.y, po.z, ct.x, ct.y, ct.z), t, -1);
+            const unsigned long long old = atomicMin(&fs.bk[o], kq);
+            atomicMin(&fs.bk2[o], old > kq ? old : kq);
         }
     }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     const unsigned long long b = fs.bk[lane];
+    const unsigned long long b2 = fs.bk2[lane];
     bd = __uint_as_float((uint32_t)(b >> 32));
+    s2 = b2 == ~0ull ? kNoSkip : __uint_as_float((uint32_t)(b2 >> 32));
     best = (b & 0x100ull) ? (int)(b & 0xFFull) : pp;
     if (valid) ev += 1u + (uint32_t)n;
+}
+
+// The float64 choice for the point with color key and previous center p:
+// the smallest key (d, k != p, k) over all K centers, d = sq_dist64 from the
+// float64 centers cen64 (LDS).  The whole wave searches, lane l taking the
+// centers l, l + 64, ...; key and p are the same in all 64 lanes, which all
+// call it.  Returns the center and its float64 distance (in all lanes).
+__device__ __forceinline__ int resolve_wave(uint32_t key, int p, int K, const double4 *cen64,
+                                            double &d64) {
+    const int lane = threadIdx.x & 63;
+    const double x = (double)((key >> 16) & 0xFFu);
+    const double y = (double)((key >> 8) & 0xFFu);
+    const double z = (double)(key & 0xFFu);
+    unsigned long long bk = ~0ull;  // the lane's smallest distance (bits; d >= 0)
+    int bt = 0;
+    for (int k = lane; k < K; k += 64) {
+        const double4 c = cen64[k];
+        const unsigned long long db =
+            (unsigned long long)__double_as_longlong(sq_dist64(x, y, z, c.x, c.y, c.z));
+        // k ascends within a lane: an equal distance wins only for k == p
+        if (db < bk || (db == bk && k == p)) {
+            bk = db;
+            bt = k;
+        }
+    }
+    const unsigned long long dmin = wave_last_u64(wave_min_u64(bk));
+    const unsigned long long tie = bk == dmin ? (bt == p ? 0ull : 1ull + (unsigned)bt) : ~0ull;
+    const unsigned long long tmin = wave_last_u64(wave_min_u64(tie));
+    d64 = __longlong_as_double((long long)dmin);
+    return tmin == 0ull ? p : (int)(tmin - 1ull);
+}
+
+// Float64 decisions of a wave's points (see kMode*).  Lane l holds the
+// float32 scan's result for its point: `fin` (a point whose scan is complete
+// here), its color key, previous center p, the chosen center best with
+// distance bd, and s2, prev, dj as for certified().  Every point whose
+// choice is not certified is decided again by resolve_wave, one point at a
+// time by the whole wave.  Returns the float64 distance from the point to
+// its (possibly new) best center, 0 where fin is false.  All 64 lanes call
+// it.
+__device__ __forceinline__ double decide64(bool fin, uint32_t key, int p, int K, int mode,
+                                           const double4 *cen64, int &best, float bd, float s2,
+                                           float prev, float dj) {
+    const int lane = threadIdx.x & 63;
+    const bool need = fin && (mode == kModeResolve ||
+                              (mode == kModeCertify && !certified(bd, s2, prev, dj)));
+    unsigned long long amb = __ballot(need);
+    double d64 = 0.0;
+    while (amb != 0ull) {  // wave-uniform
+        const int l = __builtin_ctzll(amb);
+        amb &= amb - 1ull;
+        const uint32_t kl = (uint32_t)__shfl((int)key, l, 64);
+        const int pl = __shfl(p, l, 64);
+        double dl;
+        const int bl = resolve_wave(kl, pl, K, cen64, dl);
+        if (lane == l) {
+            best = bl;
+            d64 = dl;
+        }
+    }
+    if (fin && !need) {
+        if (mode == kModeExact) {
+            d64 = (double)bd;  // integer centers and colors: the float32 distance is exact
+        } else {
+            const double4 c = cen64[best];
+            d64 = sq_dist64((double)((key >> 16) & 0xFFu), (double)((key >> 8) & 0xFFu),
+                            (double)(key & 0xFFu), c.x, c.y, c.z);
+        }
+    }
+    return d64;
 }
 
 // Queue of a block's deferred scans (LDS): points whose scan goes past the
@@ -408,6 +521,7 @@ struct DeferQueue {
     uint32_t key[kDeferCap];    // its color and count
     uint32_t cnt[kDeferCap];
     uint32_t bd[kDeferCap];     // best distance so far (float bits)
+    uint32_t s2[kDeferCap];     // second smallest distance so far (float bits)
     uint32_t pjb[kDeferCap];    // next entry << 16 | previous center << 8 | best center
 };
 
@@ -415,11 +529,13 @@ struct DeferQueue {
 // ..., each with sm_finish_wave over the row past its head (Ms holds row
 // heads of kRowPrefix entries, rows the whole rows in device memory); the
 // row entries of the first step of kDeferBatch entries are loaded together.
-// For each finished point lane 0 of the wave calls rec(idx, key, count,
-// best, best distance, evaluations made).  All threads call it, after a
-// barrier that follows the last push to the queue.
+// Each choice is then made final in float64 as decide64 does.  For each
+// finished point lane 0 of the wave calls rec(idx, key, count, best, float64
+// distance, evaluations made).  All threads call it, after a barrier that
+// follows the last push to the queue.
 template <int NT, typename Rec>
-__device__ __forceinline__ void finish_deferred(int K, const float4 *cen, const uint8_t *Ms,
+__device__ __forceinline__ void finish_deferred(int K, int mode, const float4 *cen,
+                                                const double4 *cen64, const uint8_t *Ms,
                                                 const uint8_t *__restrict__ rows,
                                                 const DeferQueue *dq, Rec &&rec) {
     constexpr int NW = NT / 64;
@@ -446,15 +562,29 @@ __device__ __forceinline__ void finish_deferred(int K, const float4 *cen, const 
             const int p = (int)((pjb >> 8) & 0xFFu);
             int best = (int)(pjb & 0xFFu);
             float bd = __uint_as_float(dq->bd[q]);
+            float s2 = __uint_as_float(dq->s2[q]);
             const uint32_t k = dq->key[q], c = dq->cnt[q];
             float x, y, z;
             unpack_key(k, x, y, z);
             const float4 cp = cen[p];
-            const float thr = sq_dist(x, y, z, cp.x, cp.y, cp.z) * kBreakScale;
+            const float prev = sq_dist(x, y, z, cp.x, cp.y, cp.z);
+            const float thr = prev * kBreakScale;
             uint32_t sev = 0;
+            float dj;
             const RowView rv{Ms + p * kRowPrefix, rows + (size_t)p * kRowStride, kRowPrefix};
-            sm_finish_wave(x, y, z, p, K, cen, rv, thr, (int)(pjb >> 16), tf[u], bd, best, sev);
-            if (lane == 0) rec(idx, k, c, best, bd, sev);  // stores and LDS atomics only
+            sm_finish_wave(x, y, z, p, K, cen, rv, thr, (int)(pjb >> 16), tf[u], bd, best, s2, dj,
+                           sev);
+            // the results are the same in every lane: the decision is wave-uniform
+            double d64;
+            if (mode == kModeResolve || (mode == kModeCertify && !certified(bd, s2, prev, dj))) {
+                best = resolve_wave(k, p, K, cen64, d64);
+            } else if (mode == kModeExact) {
+                d64 = (double)bd;
+            } else {
+                const double4 cb = cen64[best];
+                d64 = sq_dist64((double)x, (double)y, (double)z, cb.x, cb.y, cb.z);
+            }
+            if (lane == 0) rec(idx, k, c, best, d64, sev);  // stores and LDS atomics only
         }
     }
 }
@@ -481,19 +611,21 @@ __device__ __forceinline__ uint32_t sm_scan_evals(float x, float y, float z, int
     return 1u + (uint32_t)lo;
 }
 
-// Full search over all K centers with the same tie key.
+// Full search over all K centers with the same tie key; also returns the
+// second smallest distance (for certified()).
 __device__ __forceinline__ int full_scan(float x, float y, float z, int p, int K,
-                                         const float4 *cen, float &best_d, uint32_t &ev) {
+                                         const float4 *cen, float &best_d, float &s2_out,
+                                         uint32_t &ev) {
     const float4 cp = cen[p];
-    float bd = sq_dist(x, y, z, cp.x, cp.y, cp.z);
+    const float prev = sq_dist(x, y, z, cp.x, cp.y, cp.z);
+    float lo = kNoSkip, s2 = kNoSkip;
     int best = p;
     // Centers in ascending order, kScanBatch at a time (reads issued
-    // together; cen has kMaxK entries, and those past K are not taken).
-    // Under the tie rule (dist, k != p, k) a center replaces the best exactly
-    // when it is strictly nearer: a later center that ties the best has a
-    // higher index than it, or the best is still p, and both are kept; and
-    // once the best has left p it is strictly nearer than p, so p (taken in
-    // its turn, tying with the start) cannot tie it again.
+    // together; cen has kMaxK entries, and those past K are not taken).  lo
+    // and s2 are the two smallest distances; best is the first center (in
+    // index order) at the smallest one.  Under the tie rule (dist, k != p, k)
+    // that is the choice unless p ties it, and p's distance, recomputed by
+    // the same expression, is prev.
     for (int t0 = 0; t0 < K; t0 += kScanBatch) {
         float d[kScanBatch];
 #pragma unroll
@@ -503,14 +635,17 @@ __device__ __forceinline__ int full_scan(float x, float y, float z, int p, int K
         }
 #pragma unroll
         for (int e = 0; e < kScanBatch; ++e) {
-            if (t0 + e < K && d[e] < bd) {
-                bd = d[e];
-                best = t0 + e;
+            if (t0 + e < K) {
+                s2 = fminf(s2, fmaxf(d[e], lo));
+                if (d[e] < lo) best = t0 + e;
+                lo = fminf(lo, d[e]);
             }
         }
     }
+    if (prev == lo) best = p;
     ev += (uint32_t)K;
-    best_d = bd;
+    best_d = lo;
+    s2_out = s2;
     return best;
 }
 

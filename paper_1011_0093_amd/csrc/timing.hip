@@ -22,8 +22,6 @@ TimingState g_timing;
 
 namespace wsm {
 
-bool timing_attached() { return g_timing.which != 0; }
-
 bool timing_claim(int kind, hipEvent_t *begin, hipEvent_t *end) {
     if (g_timing.which != kind || g_timing.count >= g_timing.capacity) return false;
     *begin = g_timing.begin[g_timing.count];

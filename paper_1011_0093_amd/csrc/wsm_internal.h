@@ -26,7 +26,6 @@ constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // events when a caller attached events to this kernel kind; WSM_LAUNCH then
 // launches through hipExtLaunchKernelGGL, which records them at the
 // kernel's start and end.
-bool timing_attached();
 bool timing_claim(int kind, hipEvent_t *begin, hipEvent_t *end);
 
 #define WSM_LAUNCH(KIND, KERNEL, GRID, BLOCK, STREAM, ...)                                   \
@@ -47,7 +46,7 @@ struct Record {
     int32_t iters;      // iterations completed (t of the last update)
     int32_t converged;  // the Sec. 3.2 criterion (or SSE == 0) has fired
     int32_t err;        // device-side error bits
-    int32_t pad;
+    int32_t mode;       // how the centers after the update are searched (kMode*)
     double sse_last;    // SSE_t of the last completed iteration
     double pad2;
 };
@@ -71,7 +70,8 @@ static_assert(offsetof(Header, info) == 128, "header layout");
 // membership array at the end depends on the number of points.
 constexpr size_t kOffHeader = 0;
 constexpr size_t kOffPalette = 256;                                   // float4[2][256]
-constexpr size_t kOffTotals = kOffPalette + 2 * kMaxK * 16;           // u64[3][256][4]
+constexpr size_t kOffPal64 = kOffPalette + 2 * kMaxK * 16;            // double4[2][256]
+constexpr size_t kOffTotals = kOffPal64 + 2 * kMaxK * 32;             // u64[3][256][4]
 constexpr size_t kOffSsePart = kOffTotals + 3 * kMaxK * 4 * 8;        // double[2][kMaxGrid]
 constexpr size_t kOffEvalPart = kOffSsePart + 2 * kMaxGrid * 8;       // u64[2][kMaxGrid]
 constexpr size_t kOffSseHist = kOffEvalPart + 2 * kMaxGrid * 8;       // double[kHistory]
@@ -90,6 +90,7 @@ inline size_t state_bytes_for(int64_t n_points) {
 struct StateView {
     Header *hdr;
     float4 *pal;          // [2][256]
+    double4 *pal64;       // [2][256]: the same palettes in float64 (pal is their rounding)
     unsigned long long *totals;  // [3][256][4]
     double *sse_part;     // [2][kMaxGrid]
     unsigned long long *eval_part;  // [2][kMaxGrid]
@@ -106,6 +107,7 @@ inline StateView make_view(void *state) {
     StateView v;
     v.hdr = (Header *)(b + kOffHeader);
     v.pal = (float4 *)(b + kOffPalette);
+    v.pal64 = (double4 *)(b + kOffPal64);
     v.totals = (unsigned long long *)(b + kOffTotals);
     v.sse_part = (double *)(b + kOffSsePart);
     v.eval_part = (unsigned long long *)(b + kOffEvalPart);
@@ -160,6 +162,87 @@ __device__ __forceinline__ void unpack_key(uint32_t key, float &r, float &g,
     r = (float)((key >> 16) & 0xFFu);
     g = (float)((key >> 8) & 0xFFu);
     b = (float)(key & 0xFFu);
+}
+
+// ---------------------------------------------------------------------------
+// Float64 decisions.  A center is the weighted mean S_k / W_k of exact
+// integer sums (Alg. 2, last loop); its float64 value is the correctly
+// rounded mean and its float32 value the rounding of that.  The searches
+// run in float32; each point's float32 choice is kept only when it is
+// certainly the choice float64 arithmetic makes (the smallest key
+// (d, k != p, k) over all centers with d the float64 squared distance), and
+// the rest are decided again in float64 over all centers.  How a set of
+// centers is searched:
+constexpr int kModeExact = 0;    // every coordinate an integer: float32 distances are exact
+constexpr int kModeCertify = 1;  // coordinates in [0, 256): certified float32, rest in float64
+constexpr int kModeResolve = 2;  // any other center: every choice made in float64
+constexpr float kNoSkip = 3.402823466e38f;  // no row entry skipped / no second distance
+
+// Squared RGB distance in float64, summed left to right (the library is
+// built with -ffp-contract=off, so nothing is fused).
+__device__ __forceinline__ double sq_dist64(double ax, double ay, double az, double bx,
+                                            double by, double bz) {
+    const double dx = ax - bx;
+    const double dy = ay - by;
+    const double dz = az - bz;
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// Bound on |d32 - D|, d32 a squared distance computed by sq_dist from
+// float32-rounded centers (coordinates in [0, 256)) and D the exact distance
+// from the float64 centers.  Each coordinate difference is off by at most
+// 3 * 2^-17 (two center roundings of at most 2^-17 and the float32
+// subtraction), which moves D by at most 2 sqrt(3 D) 3 * 2^-17 < 2^-13 sqrt(D)
+// plus second-order terms; the three float32 roundings of the sum add at most
+// 3 * 2^-24 d.  Each term carries a margin of at least 1.5x, and the constant
+// covers distances near zero.
+__device__ __forceinline__ float f32_err(float d) {
+    return d * 0x1p-21f + __builtin_sqrtf(d) * 0x1p-13f + 0x1p-22f;
+}
+
+// Whether a float32 sort-means (or full) scan's choice is certainly the
+// float64 one.  bd: distance to the chosen center; s2: second smallest
+// distance among the evaluated centers (the previous center included;
+// kNoSkip if none); prev: distance to the previous center; dj: d(c_p, c_t)^2
+// of the first row entry the scan skipped (kNoSkip if it skipped none).
+//   (i) every other evaluated center is farther than the chosen one by more
+//       than both error bounds;
+//  (ii) every skipped center t has d(c_p, c_t)^2 >= dj (the row is sorted),
+//       so by the triangle inequality its distance from x is at least
+//       (sqrt(dj) - sqrt(d(x, c_p)^2))^2, which must exceed the chosen
+//       distance (bounds taken on the safe side; the factor 1 + 2^-16 covers
+//       the float32 square roots and the subtraction).
+__device__ __forceinline__ bool certified(float bd, float s2, float prev, float dj) {
+    const float eb = bd + f32_err(bd);
+    if (!(s2 - f32_err(s2) > eb)) return false;
+    if (dj < kNoSkip) {
+        const float r = __builtin_sqrtf(fmaxf(dj - f32_err(dj), 0.0f)) -
+                        __builtin_sqrtf(prev + f32_err(prev));
+        if (!(r > 0.0f && r * r > eb * (1.0f + 0x1p-16f))) return false;
+    }
+    return true;
+}
+
+// Mode of a set of centers (kMode*), from flags each thread collects over
+// its share of them: kFlagNonInt for a coordinate that is not an integer,
+// kFlagWild for one outside [0, 256) (or not a number).
+constexpr int kFlagNonInt = 1;
+constexpr int kFlagWild = 2;
+
+__device__ __forceinline__ int coord_flags(double v) {
+    if (!(v >= 0.0 && v < 256.0)) return kFlagWild;
+    return v != floor(v) ? kFlagNonInt : 0;
+}
+
+__device__ __forceinline__ int center_flags(double4 c) {
+    return coord_flags(c.x) | coord_flags(c.y) | coord_flags(c.z);
+}
+
+// Block-wide vote on the flags (a barrier: all threads call it).
+__device__ __forceinline__ int block_mode(int flags) {
+    const int wild = __syncthreads_or(flags & kFlagWild);
+    const int nonint = __syncthreads_or(flags & kFlagNonInt);
+    return wild ? kModeResolve : nonint ? kModeCertify : kModeExact;
 }
 
 }  // namespace wsm

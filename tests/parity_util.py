@@ -1,5 +1,11 @@
 """Comparison helpers for GPU-vs-oracle parity (the tolerances of the tests).
 
+The GPU tests hold the GPU to exact equality with the oracle for unique-color
+tables, memberships, float64 centers and pixel indices, and to SUM_RTOL for
+SSE and MSE.  The looser bounds below are the ones the method's parity
+statement asks for; check_assignment applies them where exact equality is
+not expected.
+
 * Unique-color tables: bit-exact.
 * Assignments, given identical centers: the GPU's choice k_g must satisfy
   d64(x, c_kg) <= (1 + 1e-6) min_k d64(x, c_k); and k_g must equal the
@@ -16,6 +22,11 @@ import numpy as np
 NEAR_TIE = 1e-6
 CENTER_TOL = 1e-4
 MSE_RTOL = 1e-5
+# The GPU decides every choice as float64 arithmetic on its float64 centers
+# does, so memberships and centers match the oracle exactly; SSE and MSE are
+# float64 sums taken in another order (per thread, per block, then over the
+# blocks), which moves them by about n * 1e-16 at worst.
+SUM_RTOL = 1e-10
 
 
 def unpack(keys) -> np.ndarray:

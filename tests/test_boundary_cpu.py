@@ -94,6 +94,14 @@ def test_argument_validation_before_any_launch(wsm):
     assert lib.wsm_state_views(ctypes.byref(prob), ctypes.byref(v)) == -1
     assert lib.wsm_map_pixels(ctypes.byref(prob), fake, 10, fake, fake, None, None, None) == -1
     assert lib.wsm_iterate(None, 10, 1e-4, None) == -1
+    # graph handles: invalid problem or output pointer, no handle
+    h = ctypes.c_void_p(0)
+    assert lib.wsm_iterate_graph_create(ctypes.byref(prob), 10, 1e-4, 0, ctypes.byref(h)) == -1
+    assert h.value is None
+    assert lib.wsm_iterate_graph_create(None, 10, 1e-4, 0, ctypes.byref(h)) == -1
+    assert lib.wsm_iterate_graph_create(ctypes.byref(prob), 10, 1e-4, 0, None) == -1
+    assert lib.wsm_iterate_graph_launch(None, None) == -1
+    assert lib.wsm_iterate_graph_destroy(None) == 0
 
 
 def test_iterate_rejects_bad_counts_and_eps(wsm):
