@@ -158,7 +158,11 @@ __device__ Record update_phase(const IterArgs &a, int i, float4 *cen, double4 *c
             a.sv.eval_hist[t - 1] = ev;
         }
     }
-    r.mode = block_mode(flags);  // barriers that also vote on the mode of the new centers
+    // a barrier that also votes on the mode of the new centers: updated
+    // centers are means of colors, so only a center kept from the initial
+    // palette can lie outside [0, 256) (the flag set at init)
+    const int nonint = __syncthreads_or(flags & kFlagNonInt);
+    r.mode = a.sv.hdr->wild ? kModeResolve : nonint ? kModeCertify : kModeExact;
     if (writer) {
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
@@ -273,10 +277,8 @@ __device__ void finish_block(const IterArgs &a, int i, int mode, const float4 *c
     const int tid = threadIdx.x;
     if (DEFER) {
         __syncthreads();
-        finish_deferred<NT>(a.k, mode, cen, cen64, Ms, a.sv.rows, dq,
-                            [&](uint32_t idx, uint32_t k, uint32_t c, int best, double d64,
-                                uint32_t sev) {
-            ev += sev;
+        finish_deferred<NT>(a.k, mode, cen, cen64, Ms, a.sv.rows, dq, ev,
+                            [&](uint32_t idx, uint32_t k, uint32_t c, int best, double d64) {
             sse += (double)c * d64;
             a.sv.m[idx] = (uint8_t)best;
             const unsigned long long cc = c;
@@ -341,67 +343,77 @@ __device__ void search_chunk(const IterArgs &a, int i, int mode, const float4 *c
                 }
             }
         }
-#pragma unroll
+        // one round per step, the points rotated so that the round's point
+        // is element 0 (the loop body is not unrolled)
+#pragma unroll 1
         for (int r = 0; r < kCpt; ++r) {
+            const uint32_t kr = key[0], cr = cnt[0];
+            const int pr = pm[0];
+#pragma unroll
+            for (int v = 0; v + 1 < kCpt; ++v) {
+                key[v] = key[v + 1];
+                cnt[v] = cnt[v + 1];
+                pm[v] = pm[v + 1];
+            }
             if (s0 + r * NW >= ns) break;  // block-uniform
             const int64_t slot = s0 + r * NW + wave;
             const int64_t idx = slot_point(a, slot);
             const bool valid = slot < ns && idx < a.pts.n;
             float x, y, z;
-            unpack_key(key[r], x, y, z);
+            unpack_key(kr, x, y, z);
             float bd = 0.f, s2 = kNoSkip, prev = 0.f, dj = kNoSkip;
             int best = 0;
             bool done = true;
             if (FULL) {
-                if (valid) best = full_scan(x, y, z, pm[r], a.k, cen, bd, s2, ev);
+                if (valid) best = full_scan(x, y, z, pr, a.k, cen, bd, s2, ev);
             } else if (first) {
                 // first step (every point starts from center 0, whose whole row
                 // is scanned): the full search gives the same center, and the
                 // scan's evaluation count comes from a binary search of row p
                 if (valid) {
                     uint32_t unused = 0;
-                    best = full_scan(x, y, z, pm[r], a.k, cen, bd, s2, unused);
-                    ev += sm_scan_evals(x, y, z, pm[r], a.k, cen, Ms, rs);
+                    best = full_scan(x, y, z, pr, a.k, cen, bd, s2, unused);
+                    ev += sm_scan_evals(x, y, z, pr, a.k, cen, Ms, rs);
                 }
             } else if (!DEFER) {
-                if (valid) best = sm_scan(x, y, z, pm[r], a.k, cen, Ms, rs, bd, prev, s2, dj, ev);
+                if (valid) best = sm_scan(x, y, z, pr, a.k, cen, Ms, rs, bd, prev, s2, dj, ev);
             } else {
                 // the wave's scans over the row heads together; a scan that
                 // goes past the head is deferred (or, with the queue full,
                 // carried on by its lane)
                 float thr;
                 bool more;
-                sm_scan_flat(valid, key[r], pm[r], a.k, cen, Ms, Dd, fs[wave], thr, prev, bd, s2,
+                sm_scan_flat(valid, kr, pr, a.k, cen, Ms, Dd, fs[wave], thr, prev, bd, s2,
                              dj, best, ev, more);
                 if (more) {
                     const uint32_t q = atomicAdd(&dq->n, 1u);
                     if (q < (uint32_t)kDeferCap) {
                         dq->idx[q] = (uint32_t)idx;
-                        dq->key[q] = key[r];
-                        dq->cnt[q] = cnt[r];
+                        dq->key[q] = kr;
+                        dq->cnt[q] = cr;
                         dq->bd[q] = __float_as_uint(bd);
                         dq->s2[q] = __float_as_uint(s2);
-                        dq->pjb[q] = ((uint32_t)kRowPrefix << 16) | ((uint32_t)pm[r] << 8) |
+                        dq->pjb[q] = ((uint32_t)kRowPrefix << 16) | ((uint32_t)pr << 8) |
                                      (uint32_t)best;
                         done = false;
                     } else {
-                        const RowView rv{Ms + pm[r] * rs, a.sv.rows + (size_t)pm[r] * kRowStride,
+                        const RowView rv{Ms + pr * rs, a.sv.rows + (size_t)pr * kRowStride,
                                          kRowPrefix};
                         int j = kRowPrefix;
                         dj = kNoSkip;
-                        sm_scan_range(x, y, z, pm[r], a.k, cen, rv, thr, j, a.k, bd, best, s2, dj,
+                        sm_scan_range(x, y, z, pr, a.k, cen, rv, thr, j, a.k, bd, best, s2, dj,
                                       ev);
                     }
                 }
             }
             const bool fin = valid && done;
-            const double d64 = decide64(fin, key[r], pm[r], a.k, mode, cen64, best, bd, s2, prev,
+            const double d64 = decide64(fin, kr, pr, a.k, mode, cen64, best, bd, s2, prev,
                                         dj);
             if (fin) {
                 a.sv.m[idx] = (uint8_t)best;
-                sse += (double)cnt[r] * d64;
+                sse += (double)cr * d64;
             }
-            accumulate<PACKED>(acc, best, fin, key[r], cnt[r]);
+            accumulate<PACKED>(acc, best, fin, kr, cr);
         }
     }
     finish_block<PACKED, DEFER>(a, i, mode, cen, cen64, Ms, acc, dscr, uscr, dq, sse, ev);
@@ -623,7 +635,14 @@ __global__ void init_state_kernel(StateView sv, int k, int points, int grid,
         h->grid = grid;
         h->n_points = n_points;
         h->n_pixels = n_pixels;
-        for (int j = 0; j < 4; ++j) h->reserved[j] = 0ull;
+        int flags = 0;
+        for (int c = 0; c < k; ++c)
+            flags |= center_flags(make_double4((double)init_palette[3 * c],
+                                               (double)init_palette[3 * c + 1],
+                                               (double)init_palette[3 * c + 2], 0.0));
+        h->wild = (flags & kFlagWild) ? 1 : 0;
+        h->pad = 0;
+        for (int j = 0; j < 3; ++j) h->reserved[j] = 0ull;
         Record z;
         z.iters = 0;
         z.converged = 0;

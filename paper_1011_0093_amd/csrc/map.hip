@@ -95,8 +95,18 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
                 pm[r] = sv.m[idx];
             }
         }
-#pragma unroll
+        // one round per step, the points rotated so that the round's point
+        // is element 0 (the loop body is not unrolled)
+#pragma unroll 1
         for (int r = 0; r < kCpt; ++r) {
+            const uint32_t kr = key[0], cr = cnt[0];
+            const int pr = pm[0];
+#pragma unroll
+            for (int v = 0; v + 1 < kCpt; ++v) {
+                key[v] = key[v + 1];
+                cnt[v] = cnt[v + 1];
+                pm[v] = pm[v + 1];
+            }
             if (s0 + r * NW >= ns) break;  // block-uniform
             const int64_t slot = s0 + r * NW + wave;
             const int64_t idx = ((int64_t)blockIdx.x + slot * grid) * 64 + lane;
@@ -108,12 +118,12 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
             int best = 0;
             bool more = false;
             if (FLAT) {
-                sm_scan_flat(valid, key[r], pm[r], K, cen, Ms, Dd, fs[wave], thr, prev, bd, s2, dj,
+                sm_scan_flat(valid, kr, pr, K, cen, Ms, Dd, fs[wave], thr, prev, bd, s2, dj,
                              best, ev, more);
             } else if (valid) {
                 float x, y, z;
-                unpack_key(key[r], x, y, z);
-                best = sm_scan(x, y, z, pm[r], K, cen, Ms, lds_row_stride(K), bd, prev, s2, dj,
+                unpack_key(kr, x, y, z);
+                best = sm_scan(x, y, z, pr, K, cen, Ms, lds_row_stride(K), bd, prev, s2, dj,
                                ev);
             }
             bool done = true;
@@ -121,35 +131,35 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
                 const uint32_t q = atomicAdd(&dq.n, 1u);
                 if (q < (uint32_t)kDeferCap) {
                     dq.idx[q] = (uint32_t)idx;
-                    dq.key[q] = key[r];
-                    dq.cnt[q] = cnt[r];
+                    dq.key[q] = kr;
+                    dq.cnt[q] = cr;
                     dq.bd[q] = __float_as_uint(bd);
                     dq.s2[q] = __float_as_uint(s2);
-                    dq.pjb[q] = ((uint32_t)kRowPrefix << 16) | ((uint32_t)pm[r] << 8) |
+                    dq.pjb[q] = ((uint32_t)kRowPrefix << 16) | ((uint32_t)pr << 8) |
                                 (uint32_t)best;
                     done = false;
                 } else {
                     float x, y, z;
-                    unpack_key(key[r], x, y, z);
-                    const RowView rv{Ms + pm[r] * kRowPrefix, sv.rows + (size_t)pm[r] * kRowStride,
+                    unpack_key(kr, x, y, z);
+                    const RowView rv{Ms + pr * kRowPrefix, sv.rows + (size_t)pr * kRowStride,
                                      kRowPrefix};
                     int j = kRowPrefix;
                     dj = kNoSkip;
-                    sm_scan_range(x, y, z, pm[r], K, cen, rv, thr, j, K, bd, best, s2, dj, ev);
+                    sm_scan_range(x, y, z, pr, K, cen, rv, thr, j, K, bd, best, s2, dj, ev);
                 }
             }
             const bool fin = valid && done;
-            const double d64 = decide64(fin, key[r], pm[r], K, mode, cen64, best, bd, s2, prev, dj);
+            const double d64 = decide64(fin, kr, pr, K, mode, cen64, best, bd, s2, prev, dj);
             if (fin) {
-                lut[lut_index_key(key[r])] = (uint8_t)best;
-                acc += (double)cnt[r] * d64;
+                lut[lut_index_key(kr)] = (uint8_t)best;
+                acc += (double)cr * d64;
             }
         }
     }
     if (FLAT) {
         __syncthreads();
-        finish_deferred<NT>(K, mode, cen, cen64, Ms, sv.rows, &dq,
-                            [&](uint32_t, uint32_t k, uint32_t c, int best, double d64, uint32_t) {
+        finish_deferred<NT>(K, mode, cen, cen64, Ms, sv.rows, &dq, ev,
+                            [&](uint32_t, uint32_t k, uint32_t c, int best, double d64) {
             lut[lut_index_key(k)] = (uint8_t)best;
             acc += (double)c * d64;
         });

@@ -298,14 +298,34 @@ __device__ __forceinline__ unsigned long long scan_key(float d, int t, int p) {
     return ((unsigned long long)__float_as_uint(d) << 32) | (unsigned)(t == p ? 0 : 256 + t);
 }
 
+// Distance part of a scan_key.
+__device__ __forceinline__ float key_dist(unsigned long long k) {
+    return __uint_as_float((uint32_t)(k >> 32));
+}
+
+// Whether two float32 distances of one point may be in the other order, or
+// equal, in float64: their difference is within the sum of their error
+// bounds (f32_err is increasing, so twice the larger bound covers it).  A
+// scan that meets such a pair with its best center cannot certify its
+// choice; it reports the near tie as s2 = bd (no near tie: s2 = kNoSkip),
+// which certified() rejects.
+__device__ __forceinline__ bool near_pair(float a, float b) {
+    const float hi = fmaxf(a, b), lo = fminf(a, b);
+    return hi - lo <= 2.0f * f32_err(hi);
+}
+
 // The rest of one point's scan, from row entry j, by the whole wave: lane l
 // takes entry j + l, the stop is the first entry (in row order) at or past
 // the threshold, and the entries before it are reduced with scan_key.  Every
 // argument but t_first is the same in all lanes, and all 64 lanes must call
 // it; t_first is row entry j + lane, loaded by the caller (any value where
-// j + lane >= K - 1).  The results (bd, best, the second smallest evaluated
-// distance s2, the stop entry's center distance dj -- kNoSkip if the row
-// runs out -- and the evaluations made) are the same in all lanes.
+// j + lane >= K - 1).  The results (bd, best, s2 as near_pair reports it --
+// s2 < kNoSkip on entry means a near tie was seen before -- the stop entry's
+// center distance dj, kNoSkip if the row runs out, and the evaluations made)
+// are the same in all lanes.  A near tie with the final best is caught
+// either within the 64-entry step that holds that best (every other entry
+// of the step against the step's minimum) or when a step's minimum meets
+// the best of the entries before it.
 __device__ __forceinline__ void sm_finish_wave(float x, float y, float z, int p, int K,
                                                const float4 *cen, const RowView &row, float thr,
                                                int j, int t_first, float &bd, int &best,
@@ -314,8 +334,7 @@ __device__ __forceinline__ void sm_finish_wave(float x, float y, float z, int p,
     const int n = K - 1;
     const float4 cp = cen[p];
     unsigned long long bk = scan_key(bd, best, p);
-    // second smallest so far; only its distance is used
-    unsigned long long bk2 = s2 < kNoSkip ? ((unsigned long long)__float_as_uint(s2) << 32) : ~0ull;
+    bool near = s2 < kNoSkip;
     uint32_t sev = 0;
     dj = kNoSkip;
     for (int jb = j; jb < n; jb += 64) {
@@ -331,20 +350,21 @@ __device__ __forceinline__ void sm_finish_wave(float x, float y, float z, int p,
         sev += (uint32_t)__popcll(__ballot(ok));
         const unsigned long long kl = ok ? scan_key(d, t, p) : ~0ull;
         const unsigned long long m1 = wave_last_u64(wave_min_u64(kl));
-        const unsigned long long m2 = wave_last_u64(wave_min_u64(kl == m1 ? ~0ull : kl));
-        const unsigned long long hi = bk > m1 ? bk : m1;
-        bk = bk < m1 ? bk : m1;
-        bk2 = bk2 < hi ? bk2 : hi;
-        bk2 = bk2 < m2 ? bk2 : m2;
+        if (m1 != ~0ull) {  // wave-uniform
+            const float dm = key_dist(m1);
+            const bool ln = ok && kl != m1 && near_pair(d, dm);
+            near = near || __ballot(ln) != 0ull || near_pair(dm, key_dist(bk));
+            bk = m1 < bk ? m1 : bk;
+        }
         if (first < 64) {
             const float dstop = __shfl(dpt, first, 64);
             if (jb + first < n) dj = dstop;
             break;
         }
     }
-    bd = __uint_as_float((uint32_t)(bk >> 32));
+    bd = key_dist(bk);
     best = (bk & 0x100ull) ? (int)(bk & 0xFFull) : p;
-    s2 = bk2 == ~0ull ? kNoSkip : __uint_as_float((uint32_t)(bk2 >> 32));
+    s2 = near ? bd : kNoSkip;
     evals = sev;
 }
 
@@ -353,7 +373,7 @@ struct FlatScratch {
     float4 pt[64];               // lane l: the point (x, y, z) and, as int bits, the
                                  // offset of its pair q's row entry: p * kRowPrefix - first pair
     unsigned long long bk[64];   // lane l: smallest scan_key so far
-    unsigned long long bk2[64];  // lane l: second smallest scan_key so far
+    uint32_t near[64];           // lane l: a near tie with its best was seen
     __align__(16) uint8_t head[64 * kRowPrefix];  // pair q: 1 + the lane whose pairs start at q
 };
 
@@ -373,11 +393,11 @@ struct FlatScratch {
 //   The result is the sequential scan's: bd, best, evaluations 1 + n, and
 // `more` when the break lies past entry L - 1 and the row goes on (the scan
 // then continues from entry L with threshold thr).  It also returns the
-// previous center's distance, the second smallest evaluated distance s2
-// (each pair's key goes into the point's minimum, and whichever of the two
-// loses goes into its second minimum: every key but the final minimum ends
-// there) and the center distance dj of the stop entry (kNoSkip if the row
-// runs out; unset with `more`).  Ms holds rows of kRowPrefix entries.  All
+// previous center's distance, s2 as near_pair reports it (each pair's key
+// goes into the point's minimum, and is compared with the minimum it meets
+// there: of the final minimum and any key near it, the later of the two to
+// arrive meets the other or a key between them) and the center distance dj
+// of the stop entry (kNoSkip if the row runs out; unset with `more`).  Ms holds rows of kRowPrefix entries.  All
 // 64 lanes call it.  Lanes of one wave exchange data through LDS here; LDS
 // operations of a wave take effect in issue order, and signal fences keep
 // the compiler from reordering them.
@@ -412,15 +432,23 @@ __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, in
     h4[lane + 64] = make_uint4(0u, 0u, 0u, 0u);
     fs.pt[lane] = make_float4(x, y, z, __int_as_float(pp * kRowPrefix - excl));
     fs.bk[lane] = scan_key(prev, pp, pp);
-    fs.bk2[lane] = ~0ull;
+    fs.near[lane] = 0u;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if (n > 0) fs.head[excl] = (uint8_t)(lane + 1);
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     uint32_t carry = 0u;
+    // A pair's key is compared with the minimum it met one iteration late,
+    // so the wait for the returned value overlaps the next iteration's LDS
+    // reads.
+    int pend_o = -1;
+    unsigned long long pend_old = 0ull, pend_kq = 0ull;
     for (int q0 = 0; q0 < total; q0 += 64) {  // wave-uniform
         const int q = q0 + lane;
         const bool act = q < total;
-        uint32_t o1 = wave_incl_max(act ? (uint32_t)fs.head[q] : 0u);
+        const uint32_t hq = act ? (uint32_t)fs.head[q] : 0u;
+        if (pend_o >= 0 && near_pair(key_dist(pend_kq), key_dist(pend_old))) fs.near[pend_o] = 1u;
+        pend_o = -1;
+        uint32_t o1 = wave_incl_max(hq);
         o1 = o1 > carry ? o1 : carry;
         carry = wave_last_u32(o1);
         if (act) {
@@ -428,17 +456,16 @@ __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, in
             const float4 po = fs.pt[o];
             const int t = Ms[__float_as_int(po.w) + q];
             const float4 ct = cen[t];
-            const unsigned long long kq =
-                scan_key(sq_dist(po.x, po.y, po.z, ct.x, ct.y, ct.z), t, -1);
-            const unsigned long long old = atomicMin(&fs.bk[o], kq);
-            atomicMin(&fs.bk2[o], old > kq ? old : kq);
+            pend_kq = scan_key(sq_dist(po.x, po.y, po.z, ct.x, ct.y, ct.z), t, -1);
+            pend_old = atomicMin(&fs.bk[o], pend_kq);
+            pend_o = o;
         }
     }
+    if (pend_o >= 0 && near_pair(key_dist(pend_kq), key_dist(pend_old))) fs.near[pend_o] = 1u;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     const unsigned long long b = fs.bk[lane];
-    const unsigned long long b2 = fs.bk2[lane];
-    bd = __uint_as_float((uint32_t)(b >> 32));
-    s2 = b2 == ~0ull ? kNoSkip : __uint_as_float((uint32_t)(b2 >> 32));
+    bd = key_dist(b);
+    s2 = fs.near[lane] != 0u ? bd : kNoSkip;
     best = (b & 0x100ull) ? (int)(b & 0xFFull) : pp;
     if (valid) ev += 1u + (uint32_t)n;
 }
@@ -448,8 +475,13 @@ __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, in
 // float64 centers cen64 (LDS).  The whole wave searches, lane l taking the
 // centers l, l + 64, ...; key and p are the same in all 64 lanes, which all
 // call it.  Returns the center and its float64 distance (in all lanes).
-__device__ __forceinline__ int resolve_wave(uint32_t key, int p, int K, const double4 *cen64,
-                                            double &d64) {
+// Rare, so kept out of line (the result comes back in registers).
+struct Choice64 {
+    double d64;
+    int best;
+};
+
+__device__ __noinline__ Choice64 resolve_wave(uint32_t key, int p, int K, const double4 *cen64) {
     const int lane = threadIdx.x & 63;
     const double x = (double)((key >> 16) & 0xFFu);
     const double y = (double)((key >> 8) & 0xFFu);
@@ -469,8 +501,10 @@ __device__ __forceinline__ int resolve_wave(uint32_t key, int p, int K, const do
     const unsigned long long dmin = wave_last_u64(wave_min_u64(bk));
     const unsigned long long tie = bk == dmin ? (bt == p ? 0ull : 1ull + (unsigned)bt) : ~0ull;
     const unsigned long long tmin = wave_last_u64(wave_min_u64(tie));
-    d64 = __longlong_as_double((long long)dmin);
-    return tmin == 0ull ? p : (int)(tmin - 1ull);
+    Choice64 c;
+    c.d64 = __longlong_as_double((long long)dmin);
+    c.best = tmin == 0ull ? p : (int)(tmin - 1ull);
+    return c;
 }
 
 // Float64 decisions of a wave's points (see kMode*).  Lane l holds the
@@ -494,11 +528,10 @@ __device__ __forceinline__ double decide64(bool fin, uint32_t key, int p, int K,
         amb &= amb - 1ull;
         const uint32_t kl = (uint32_t)__shfl((int)key, l, 64);
         const int pl = __shfl(p, l, 64);
-        double dl;
-        const int bl = resolve_wave(kl, pl, K, cen64, dl);
+        const Choice64 c = resolve_wave(kl, pl, K, cen64);
         if (lane == l) {
-            best = bl;
-            d64 = dl;
+            best = c.best;
+            d64 = c.d64;
         }
     }
     if (fin && !need) {
@@ -525,19 +558,25 @@ struct DeferQueue {
     uint32_t pjb[kDeferCap];    // next entry << 16 | previous center << 8 | best center
 };
 
-// Finishes a block's deferred scans: wave w takes queue entries w, w + NW,
-// ..., each with sm_finish_wave over the row past its head (Ms holds row
-// heads of kRowPrefix entries, rows the whole rows in device memory); the
-// row entries of the first step of kDeferBatch entries are loaded together.
-// Each choice is then made final in float64 as decide64 does.  For each
-// finished point lane 0 of the wave calls rec(idx, key, count, best, float64
-// distance, evaluations made).  All threads call it, after a barrier that
-// follows the last push to the queue.
+// Finishes a block's deferred scans (Ms holds row heads of kRowPrefix
+// entries, rows the whole rows in device memory), in three phases:
+//   1. wave w takes queue entries w, w + NW, ..., each with sm_finish_wave
+//      over the row past its head (the row entries of the first step of
+//      kDeferBatch entries are loaded together), and writes the choice and
+//      whether it is certified back into the entry; evaluations go to ev of
+//      lane 0;
+//   2. one thread per certified entry computes its float64 distance;
+//   3. the other entries are decided by resolve_wave, one wave each.
+// For each finished point rec(idx, key, count, best, float64 distance) is
+// called by one thread (stores and LDS atomics only).  All threads call it,
+// after a barrier that follows the last push to the queue.
+constexpr uint32_t kDeferUnsure = 1u << 16;  // entry flag after phase 1
+
 template <int NT, typename Rec>
 __device__ __forceinline__ void finish_deferred(int K, int mode, const float4 *cen,
                                                 const double4 *cen64, const uint8_t *Ms,
-                                                const uint8_t *__restrict__ rows,
-                                                const DeferQueue *dq, Rec &&rec) {
+                                                const uint8_t *__restrict__ rows, DeferQueue *dq,
+                                                uint32_t &ev, Rec &&rec) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t nd = dq->n < (uint32_t)kDeferCap ? dq->n : (uint32_t)kDeferCap;
@@ -554,37 +593,65 @@ __device__ __forceinline__ void finish_deferred(int K, int mode, const float4 *c
                 if (jj < K - 1) tf[u] = rows[row + jj];
             }
         }
-#pragma unroll
+        // one entry per step; tf is rotated so that its first element is the
+        // current entry's (the loop body is not unrolled)
+#pragma unroll 1
         for (int u = 0; u < kDeferBatch; ++u) {
+            const int t_first = tf[0];
+#pragma unroll
+            for (int v = 0; v + 1 < kDeferBatch; ++v) tf[v] = tf[v + 1];
             const uint32_t q = q0 + (uint32_t)(u * NW);
             if (q >= nd) break;  // wave-uniform
-            const uint32_t idx = dq->idx[q], pjb = dq->pjb[q];
+            const uint32_t pjb = dq->pjb[q];
             const int p = (int)((pjb >> 8) & 0xFFu);
             int best = (int)(pjb & 0xFFu);
             float bd = __uint_as_float(dq->bd[q]);
             float s2 = __uint_as_float(dq->s2[q]);
-            const uint32_t k = dq->key[q], c = dq->cnt[q];
             float x, y, z;
-            unpack_key(k, x, y, z);
+            unpack_key(dq->key[q], x, y, z);
             const float4 cp = cen[p];
             const float prev = sq_dist(x, y, z, cp.x, cp.y, cp.z);
             const float thr = prev * kBreakScale;
             uint32_t sev = 0;
             float dj;
             const RowView rv{Ms + p * kRowPrefix, rows + (size_t)p * kRowStride, kRowPrefix};
-            sm_finish_wave(x, y, z, p, K, cen, rv, thr, (int)(pjb >> 16), tf[u], bd, best, s2, dj,
-                           sev);
-            // the results are the same in every lane: the decision is wave-uniform
-            double d64;
-            if (mode == kModeResolve || (mode == kModeCertify && !certified(bd, s2, prev, dj))) {
-                best = resolve_wave(k, p, K, cen64, d64);
-            } else if (mode == kModeExact) {
-                d64 = (double)bd;
-            } else {
-                const double4 cb = cen64[best];
-                d64 = sq_dist64((double)x, (double)y, (double)z, cb.x, cb.y, cb.z);
+            sm_finish_wave(x, y, z, p, K, cen, rv, thr, (int)(pjb >> 16), t_first, bd, best, s2,
+                           dj, sev);
+            // the results are the same in every lane
+            const bool sure =
+                mode == kModeExact || (mode == kModeCertify && certified(bd, s2, prev, dj));
+            if (lane == 0) {
+                ev += sev;
+                dq->bd[q] = __float_as_uint(bd);
+                dq->pjb[q] = (sure ? 0u : kDeferUnsure) | ((uint32_t)p << 8) | (uint32_t)best;
             }
-            if (lane == 0) rec(idx, k, c, best, d64, sev);  // stores and LDS atomics only
+        }
+    }
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < nd; q += NT) {
+        const uint32_t pjb = dq->pjb[q];
+        if (pjb & kDeferUnsure) continue;
+        const int best = (int)(pjb & 0xFFu);
+        const uint32_t k = dq->key[q];
+        double d64;
+        if (mode == kModeExact) {
+            d64 = (double)__uint_as_float(dq->bd[q]);  // exact (integer centers)
+        } else {
+            const double4 cb = cen64[best];
+            d64 = sq_dist64((double)((k >> 16) & 0xFFu), (double)((k >> 8) & 0xFFu),
+                            (double)(k & 0xFFu), cb.x, cb.y, cb.z);
+        }
+        rec(dq->idx[q], k, dq->cnt[q], best, d64);
+    }
+    for (uint32_t c0 = (uint32_t)wave * 64u; c0 < nd; c0 += NW * 64u) {
+        const uint32_t q = c0 + (uint32_t)lane;
+        unsigned long long unsure = __ballot(q < nd && (dq->pjb[q] & kDeferUnsure) != 0u);
+        while (unsure != 0ull) {  // wave-uniform
+            const uint32_t qq = c0 + (uint32_t)__builtin_ctzll(unsure);
+            unsure &= unsure - 1ull;
+            const uint32_t k = dq->key[qq];
+            const Choice64 c = resolve_wave(k, (int)((dq->pjb[qq] >> 8) & 0xFFu), K, cen64);
+            if (lane == 0) rec(dq->idx[qq], k, dq->cnt[qq], c.best, c.d64);
         }
     }
 }

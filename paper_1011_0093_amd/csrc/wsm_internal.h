@@ -59,7 +59,9 @@ struct Header {
     int32_t grid;
     int64_t n_points;
     int64_t n_pixels;
-    uint64_t reserved[4];
+    int32_t wild;       // the initial palette has a coordinate outside [0, 256)
+    int32_t pad;
+    uint64_t reserved[3];
     Record rec[2];      // bytes 64..127
     int32_t info[4];    // bytes 128..143: public copy {iters, converged, err, 0}
 };
@@ -195,10 +197,16 @@ __device__ __forceinline__ double sq_dist64(double ax, double ay, double az, dou
 // subtraction), which moves D by at most 2 sqrt(3 D) 3 * 2^-17 < 2^-13 sqrt(D)
 // plus second-order terms; the three float32 roundings of the sum add at most
 // 3 * 2^-24 d.  Each term carries a margin of at least 1.5x, and the constant
-// covers distances near zero.
+// covers distances near zero.  The square root is the hardware one (within a
+// few ulp), which the margins absorb.
 __device__ __forceinline__ float f32_err(float d) {
-    return d * 0x1p-21f + __builtin_sqrtf(d) * 0x1p-13f + 0x1p-22f;
+    return d * 0x1p-21f + __builtin_amdgcn_sqrtf(d) * 0x1p-13f + 0x1p-22f;
 }
+
+// The same bound without the square root: distances between colors and
+// centers in [0, 256)^3 are below 3 * 256^2, so sqrt(d) < 444 and
+// 2^-13 sqrt(d) + 2^-22 < 2^-4.
+__device__ __forceinline__ float f32_err_max(float d) { return d * 0x1p-21f + 0x1p-4f; }
 
 // Whether a float32 sort-means (or full) scan's choice is certainly the
 // float64 one.  bd: distance to the chosen center; s2: second smallest
@@ -210,14 +218,30 @@ __device__ __forceinline__ float f32_err(float d) {
 //  (ii) every skipped center t has d(c_p, c_t)^2 >= dj (the row is sorted),
 //       so by the triangle inequality its distance from x is at least
 //       (sqrt(dj) - sqrt(d(x, c_p)^2))^2, which must exceed the chosen
-//       distance (bounds taken on the safe side; the factor 1 + 2^-16 covers
-//       the float32 square roots and the subtraction).
+//       distance.  The chosen distance is at most the previous center's, so
+//       it suffices that (sqrt(dj') - sqrt(prev'))^2 > prev' (1 + 2^-16),
+//       primes marking the bounds taken on the safe side; that holds when
+//       dj' > 4 prev' (1 + 2^-15).  Otherwise the chosen distance itself is
+//       compared (the factor 1 + 2^-16 covers the float32 square roots and
+//       the subtraction).
+// Each test is first tried with f32_err_max, which needs no square root
+// and decides almost every point; certified_exact, out of line, redoes the
+// tests with f32_err only for the rest.
+__device__ __noinline__ bool certified_exact(float bd, float s2, float prev, float dj);
+
 __device__ __forceinline__ bool certified(float bd, float s2, float prev, float dj) {
-    const float eb = bd + f32_err(bd);
-    if (!(s2 - f32_err(s2) > eb)) return false;
+    const bool i_fast = s2 - f32_err_max(s2) > bd + f32_err_max(bd);
+    const bool ii_fast =
+        !(dj < kNoSkip) || dj - f32_err_max(dj) > 4.0f * (prev + f32_err_max(prev)) * (1.0f + 0x1p-15f);
+    return (i_fast && ii_fast) || certified_exact(bd, s2, prev, dj);
+}
+
+__device__ __noinline__ bool certified_exact(float bd, float s2, float prev, float dj) {
+    if (!(s2 - f32_err(s2) > bd + f32_err(bd))) return false;
     if (dj < kNoSkip) {
-        const float r = __builtin_sqrtf(fmaxf(dj - f32_err(dj), 0.0f)) -
-                        __builtin_sqrtf(prev + f32_err(prev));
+        const float eb = bd + f32_err(bd);
+        const float r = __builtin_amdgcn_sqrtf(fmaxf(dj - f32_err(dj), 0.0f)) -
+                        __builtin_amdgcn_sqrtf(prev + f32_err(prev));
         if (!(r > 0.0f && r * r > eb * (1.0f + 0x1p-16f))) return false;
     }
     return true;

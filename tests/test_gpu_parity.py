@@ -149,12 +149,15 @@ def _check_step(colors, counts, n_pix, m_prev, c_prev, m_gpu, c_gpu64, c_gpu32, 
     return dict(t=t, evals_gpu=int(ev_gpu), evals_ref=ev_ref)
 
 
-def _lockstep(img, K, seed, iters, full=False, check_evals=True, indices=None):
+def _lockstep(img, K, seed, iters, full=False, check_evals=True, indices=None, palette=None):
     wsm = _wsm()
     g, col, cnt, colors, counts = _gpu_table(img)
     n_pix = img.shape[0] * img.shape[1]
-    idx = synth.init_indices(seed, len(colors), K) if indices is None else indices
-    pal = wsm.palette_from_indices(col, idx)
+    if palette is not None:
+        pal = torch.from_numpy(np.ascontiguousarray(palette, dtype=np.float32)).cuda()
+    else:
+        idx = synth.init_indices(seed, len(colors), K) if indices is None else indices
+        pal = wsm.palette_from_indices(col, idx)
     m_prev = np.zeros(len(colors), dtype=np.uint8)
     c_prev = pal.cpu().numpy().astype(np.float64)
     stats = []
@@ -225,6 +228,39 @@ def test_lockstep_tiny_table_k256():
     img[:, :4] = img[:1, :4]          # some repeated colors
     _say("lockstep tiny random image 24x20 K 256")
     stats = _lockstep(img, 256, 5, 4)
+    print(stats[-1])
+
+
+def _fractional_duplicates(colors, K, seed):
+    """K centers in identical pairs at fractional positions near sampled
+    colors: every color near a pair ties between its two members, so the
+    float32 choice is never certified there and float64 decides."""
+    rng = np.random.default_rng(seed)
+    base = synth.unpack_keys_to_palette(colors[synth.init_indices(seed, len(colors), K // 2)])
+    base = np.clip(base + rng.choice([-0.375, 0.25, 0.625], size=base.shape), 0, 255)
+    return np.repeat(base, 2, axis=0).astype(np.float32)
+
+
+@pytest.mark.parametrize("name,K", [("small", 32), ("medium", 64), ("medium", 256)])
+def test_lockstep_duplicate_fractional_centers(name, K):
+    img = synth.workload_image(name, 0)
+    colors, _ = oracle.reduce_colors(img)
+    _say("lockstep", name, "K", K, "pairs of identical fractional centers")
+    stats = _lockstep(img, K, 0, 4, palette=_fractional_duplicates(colors, K, 0))
+    print(stats[-1])
+
+
+@pytest.mark.parametrize("K", [32, 200])
+def test_lockstep_palette_outside_the_cube(K):
+    """A center outside [0, 255]^3 voids the float32 error bound: every
+    choice is then made in float64, and the results still match."""
+    img = synth.workload_image("medium", 2)
+    colors, _ = oracle.reduce_colors(img)
+    pal = synth.unpack_keys_to_palette(colors[synth.init_indices(2, len(colors), K)])
+    pal = pal.astype(np.float32)
+    pal[1] = (300.0, -20.0, 128.5)
+    _say("lockstep medium seed 2 K", K, "one center outside the color cube")
+    stats = _lockstep(img, K, 2, 4, palette=pal)
     print(stats[-1])
 
 
