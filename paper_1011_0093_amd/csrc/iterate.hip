@@ -364,16 +364,18 @@ __device__ void search_chunk(const IterArgs &a, int i, int mode, const float4 *c
             float bd = 0.f, s2 = kNoSkip, prev = 0.f, dj = kNoSkip;
             int best = 0;
             bool done = true;
-            if (FULL) {
-                if (valid) best = full_scan(x, y, z, pr, a.k, cen, bd, s2, ev);
-            } else if (first) {
-                // first step (every point starts from center 0, whose whole row
-                // is scanned): the full search gives the same center, and the
-                // scan's evaluation count comes from a binary search of row p
+            if (FULL || first) {
+                // the full search; or in the first step (every point starts
+                // from center 0, whose whole row is scanned) the full search
+                // gives the same center, and the scan's evaluation count
+                // comes from a binary search of row p
                 if (valid) {
-                    uint32_t unused = 0;
-                    best = full_scan(x, y, z, pr, a.k, cen, bd, s2, unused);
-                    ev += sm_scan_evals(x, y, z, pr, a.k, cen, Ms, rs);
+                    uint32_t fev = 0;
+                    if (mode == kModeExact)
+                        best = full_scan<false>(x, y, z, pr, a.k, cen, bd, s2, fev);
+                    else
+                        best = full_scan<true>(x, y, z, pr, a.k, cen, bd, s2, fev);
+                    ev += FULL ? fev : sm_scan_evals(x, y, z, pr, a.k, cen, Ms, rs);
                 }
             } else if (!DEFER) {
                 if (valid) best = sm_scan(x, y, z, pr, a.k, cen, Ms, rs, bd, prev, s2, dj, ev);

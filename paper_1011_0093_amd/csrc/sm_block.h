@@ -678,21 +678,28 @@ __device__ __forceinline__ uint32_t sm_scan_evals(float x, float y, float z, int
     return 1u + (uint32_t)lo;
 }
 
-// Full search over all K centers with the same tie key; also returns the
-// second smallest distance (for certified()).
+// Full search over all K centers with the same tie key; with TOP2 it also
+// returns the second smallest distance (for certified()), otherwise s2_out
+// is left alone (exact mode needs no certificate).
+template <bool TOP2>
 __device__ __forceinline__ int full_scan(float x, float y, float z, int p, int K,
                                          const float4 *cen, float &best_d, float &s2_out,
                                          uint32_t &ev) {
     const float4 cp = cen[p];
     const float prev = sq_dist(x, y, z, cp.x, cp.y, cp.z);
-    float lo = kNoSkip, s2 = kNoSkip;
+    float lo = TOP2 ? kNoSkip : prev, s2 = kNoSkip;
     int best = p;
     // Centers in ascending order, kScanBatch at a time (reads issued
-    // together; cen has kMaxK entries, and those past K are not taken).  lo
-    // and s2 are the two smallest distances; best is the first center (in
-    // index order) at the smallest one.  Under the tie rule (dist, k != p, k)
-    // that is the choice unless p ties it, and p's distance, recomputed by
-    // the same expression, is prev.
+    // together; cen has kMaxK entries, and those past K are not taken).
+    // Under the tie rule (dist, k != p, k) a center replaces the best exactly
+    // when it is strictly nearer: a later center that ties the best has a
+    // higher index than it, or the best is still p, and both are kept; and
+    // once the best has left p it is strictly nearer than p, so p (taken in
+    // its turn, tying with the start) cannot tie it again.  With TOP2 the
+    // scan starts empty instead, so that p is counted once among the two
+    // smallest distances, and p wins a tie with the first center at the
+    // smallest distance afterwards (its distance, recomputed by the same
+    // expression, is prev).
     for (int t0 = 0; t0 < K; t0 += kScanBatch) {
         float d[kScanBatch];
 #pragma unroll
@@ -703,16 +710,18 @@ __device__ __forceinline__ int full_scan(float x, float y, float z, int p, int K
 #pragma unroll
         for (int e = 0; e < kScanBatch; ++e) {
             if (t0 + e < K) {
-                s2 = fminf(s2, fmaxf(d[e], lo));
-                if (d[e] < lo) best = t0 + e;
-                lo = fminf(lo, d[e]);
+                if (TOP2) s2 = fminf(s2, fmaxf(d[e], lo));
+                if (d[e] < lo) {
+                    lo = d[e];
+                    best = t0 + e;
+                }
             }
         }
     }
-    if (prev == lo) best = p;
+    if (TOP2 && prev == lo) best = p;
     ev += (uint32_t)K;
     best_d = lo;
-    s2_out = s2;
+    if (TOP2) s2_out = s2;
     return best;
 }
 
