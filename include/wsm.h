@@ -74,6 +74,22 @@ int wsm_reduce_colors(const uint8_t *rgb, int64_t n_pixels, uint32_t *colors,
                       void *workspace, size_t workspace_bytes,
                       hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * reduction with the library's own workspace, a device array of
+ * wsm_reduce_workspace_bytes(WSM_STATIC_MAX_PIXELS) bytes (35.7 MB) that
+ * every GPU the library runs on holds until the process ends.  The call
+ * itself allocates and frees nothing; its first call on a device (with that
+ * device current) looks up the array's address there.  Arguments as for
+ * wsm_reduce_colors; n_pixels > WSM_STATIC_MAX_PIXELS returns WSM_ENOSPC.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (on different streams, or from different threads without ordering)
+ * race and must not be made; calls ordered on one stream are fine. */
+#define WSM_STATIC_MAX_PIXELS (1 << 24)
+int wsm_reduce_colors_static(const uint8_t *rgb, int64_t n_pixels,
+                             uint32_t *colors, uint32_t *counts, int64_t cap,
+                             int32_t *n_unique, hipStream_t stream);
+
 /* ------------------------------------------------------------------ */
 /* Clustering state.  A caller-owned block of device memory holds the
  * palette, the memberships m[], per-iteration records and scratch; this

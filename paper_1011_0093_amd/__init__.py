@@ -92,6 +92,7 @@ def _load():
     lib.wsm_timing_attach.argtypes = [I32, I32]
     lib.wsm_timing_read.argtypes = [ctypes.POINTER(ctypes.c_float), I32, ctypes.POINTER(I32)]
     lib.wsm_timing_detach.argtypes = []
+    lib.wsm_reduce_colors_static.argtypes = [P, I64, P, P, I64, P, P]
     lib.wsm_iterate_graph_create.argtypes = [PP, I32, D, I32, ctypes.POINTER(P)]
     lib.wsm_iterate_graph_launch.argtypes = [P, P]
     lib.wsm_iterate_graph_destroy.argtypes = [P]
@@ -99,7 +100,7 @@ def _load():
               "wsm_init_pixels", "wsm_iterate", "wsm_iterate_full", "wsm_state_views",
               "wsm_map_pixels", "wsm_gather_palette", "wsm_timing_attach", "wsm_timing_read",
               "wsm_timing_detach", "wsm_iterate_graph_create", "wsm_iterate_graph_launch",
-              "wsm_iterate_graph_destroy"):
+              "wsm_iterate_graph_destroy", "wsm_reduce_colors_static"):
         getattr(lib, f).restype = I32
     return lib
 
@@ -149,6 +150,17 @@ def reduce_colors_into(img: torch.Tensor, colors: torch.Tensor, counts: torch.Te
     _check(_lib.wsm_reduce_colors(_ptr(img), n, _ptr(colors), _ptr(counts), colors.numel(),
                                   _ptr(n_unique), _ptr(workspace), workspace.numel(), _stream()),
            "wsm_reduce_colors")
+
+
+def reduce_colors_static_into(img: torch.Tensor, colors: torch.Tensor, counts: torch.Tensor,
+                              n_unique: torch.Tensor) -> None:
+    """Allocation-free form (wsm_reduce_colors_static): the library's own
+    workspace, images of at most 2^24 pixels; asynchronous on the current
+    stream."""
+    img = _dev(img, torch.uint8, "img")
+    n = img.numel() // 3
+    _check(_lib.wsm_reduce_colors_static(_ptr(img), n, _ptr(colors), _ptr(counts), colors.numel(),
+                                         _ptr(n_unique), _stream()), "wsm_reduce_colors_static")
 
 
 def reduce_colors(img: torch.Tensor):

@@ -18,6 +18,8 @@
 //              ascending order, and the slice's place in the output comes
 //              from a decoupled look-back over the slices before it, 64
 //              predecessors per step.
+#include <mutex>
+
 #include "wave_ops.h"
 #include "wsm_internal.h"
 
@@ -42,8 +44,8 @@ struct ReduceLayout {
     size_t off_keys, off_info, off_status, bytes;
 };
 
-static ReduceLayout reduce_layout(int64_t n) {
-    ReduceLayout L;
+constexpr ReduceLayout reduce_layout(int64_t n) {
+    ReduceLayout L{};
     // Small images get small tiles so that enough blocks run.
     int ppt = 1;
     while (ppt < kMaxPpt && (int64_t)kPartThreads * ppt * 2 * 256 <= n) ppt *= 2;
@@ -338,6 +340,10 @@ extern "C" int wsm_reduce_workspace_bytes(int64_t n_pixels, size_t *bytes) {
     return WSM_OK;
 }
 
+static int reduce_launch(const uint8_t *rgb, int64_t n_pixels, uint32_t *colors,
+                         uint32_t *counts, int32_t *n_unique, void *workspace,
+                         const ReduceLayout &L, hipStream_t stream);
+
 extern "C" int wsm_reduce_colors(const uint8_t *rgb, int64_t n_pixels, uint32_t *colors,
                                  uint32_t *counts, int64_t cap, int32_t *n_unique,
                                  void *workspace, size_t workspace_bytes, hipStream_t stream) {
@@ -348,6 +354,12 @@ extern "C" int wsm_reduce_colors(const uint8_t *rgb, int64_t n_pixels, uint32_t 
     if (((uintptr_t)workspace & 15u) != 0u) return WSM_EINVAL;
     const ReduceLayout L = reduce_layout(n_pixels);
     if (workspace_bytes < L.bytes) return WSM_ENOSPC;
+    return reduce_launch(rgb, n_pixels, colors, counts, n_unique, workspace, L, stream);
+}
+
+static int reduce_launch(const uint8_t *rgb, int64_t n_pixels, uint32_t *colors,
+                         uint32_t *counts, int32_t *n_unique, void *workspace,
+                         const ReduceLayout &L, hipStream_t stream) {
     char *ws = (char *)workspace;
     uint16_t *keys16 = (uint16_t *)(ws + L.off_keys);
     uint32_t *info = (uint32_t *)(ws + L.off_info);
@@ -369,4 +381,61 @@ extern "C" int wsm_reduce_colors(const uint8_t *rgb, int64_t n_pixels, uint32_t 
                L.ntiles, L.tile, colors, counts, status, n_unique, err);
     if (hipGetLastError() != hipSuccess) return WSM_EHIP;
     return WSM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of wsm_reduce_colors: its workspace is the
+// file-scope device array `scratch`, sized for the largest image it takes
+// (WSM_STATIC_MAX_PIXELS).  Every GPU the library runs on holds its own
+// copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, so its device address is looked up (hipGetSymbolAddress) the
+// first time the entry point runs on a device, with that device current,
+// and kept per device; only that address is passed to the kernels.  The
+// partition kernel clears the look-back flags and the error word it uses,
+// so nothing left by an earlier call needs clearing.
+constexpr size_t kScratchBytes = reduce_layout(WSM_STATIC_MAX_PIXELS).bytes;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device.
+int scratch_address(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) {
+        (void)hipGetLastError();
+        return WSM_EHIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return WSM_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return WSM_OK;
+}
+
+}  // namespace
+
+extern "C" int wsm_reduce_colors_static(const uint8_t *rgb, int64_t n_pixels, uint32_t *colors,
+                                        uint32_t *counts, int64_t cap, int32_t *n_unique,
+                                        hipStream_t stream) {
+    if (!rgb || !colors || !counts || !n_unique) return WSM_EINVAL;
+    if (n_pixels < 1) return WSM_EINVAL;
+    if (n_pixels > (int64_t)WSM_STATIC_MAX_PIXELS) return WSM_ENOSPC;
+    const int64_t need_cap = n_pixels < (1ll << 24) ? n_pixels : (1ll << 24);
+    if (cap < need_cap) return WSM_ENOSPC;
+    const ReduceLayout L = reduce_layout(n_pixels);
+    if (L.bytes > kScratchBytes) return WSM_ENOSPC;
+    void *ws = nullptr;
+    const int rc = scratch_address(&ws);
+    if (rc != WSM_OK) return rc;
+    return reduce_launch(rgb, n_pixels, colors, counts, n_unique, ws, L, stream);
 }
