@@ -11,13 +11,17 @@ initial palette (same trajectory, so equal MSE by construction; checked).
 One step = one pass of the whole hot path over the image: unique-color
 reduction, then for each K: initial palette from the seeded random subset,
 state init, iterations, pixel map (with MSE).  Inputs are resident in HBM
-before the timed region.
+before the timed region.  Every kernel is launched directly; the same step
+replayed from caller-owned HIP graphs is reported beside it.
 
 Prints ONE JSON line.  Extra objects: per-K details, the full-search
 comparators, the roofline of the dominant kernel (measured live with HIP
 events around each of its launches, in a separate pass over the same
-workload), the reduction/map rooflines on the 4096x4096 workload, and the
-FP64 CPU oracle timed on this host.
+workload), the 256x256 workload (WSM-C and the fixed 10-iteration variant),
+the 4096x4096 workload (reduction and map rooflines, whole-image
+throughput), the K-scaling study (time and evaluations per iteration for
+K = 2..256, sort-means against the full search), and the FP64 CPU oracle
+timed on this host.
 """
 
 from __future__ import annotations
@@ -108,6 +112,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--no-k-sweep", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-oracle-timings", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -199,6 +207,51 @@ def main():
     ms_step = e0.elapsed_time(e1) / args.steps
     ms_step_wall = wall * 1000.0 / args.steps
 
+    # ---- the same step with each K's iterate launches replayed from a
+    # caller-owned HIP graph, recorded once outside the timed region (the
+    # same image every step, so the recorded arguments stay valid)
+    graph_leg = None
+    if not args.no_graph:
+        graphs = {K: states[K].graph(MAX_ITERS, EPS) for K in Ks}
+        ref64 = {K: states[K].palette64().cpu() for K in Ks}
+
+        def step_graph():
+            wsm.reduce_colors_into(img, colors, counts, nu, ws)
+            n_u = int(nu.item())
+            col_g, cnt_g = colors[:n_u], counts[:n_u]
+            o = 0
+            for K in Ks:
+                idx_host[o:o + K] = torch.from_numpy(
+                    synth.init_indices(args.seed, n_u, K).astype(np.int32))
+                o += K
+            idx_dev.copy_(idx_host, non_blocking=True)
+            o = 0
+            for K in Ks:
+                pal_g = wsm.palette_from_indices(col_g, idx_dev[o:o + K])
+                o += K
+                st_g = wsm.init(col_g, cnt_g, N, pal_g, reuse=states[K])
+                graphs[K].launch()
+                wsm.map_pixels(st_g, img, lut=lut)
+
+        for _ in range(args.warmup):
+            step_graph()
+        torch.cuda.synchronize()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record(stream)
+        for _ in range(args.steps):
+            step_graph()
+        g1.record(stream)
+        torch.cuda.synchronize()
+        ms_graph = g0.elapsed_time(g1) / args.steps
+        same = all(torch.equal(states[K].palette64().cpu(), ref64[K]) for K in Ks)
+        for gr in graphs.values():
+            gr.close()
+        graph_leg = dict(ms_per_step=ms_graph, images_per_s=len(Ks) / (ms_graph * 1e-3),
+                         equal_to_direct=bool(same),
+                         note="iterate launches of each K replayed from a caller-owned HIP graph "
+                              "(wsm_iterate_graph_*); reduce, init and map launched directly")
+
     per_k = {}
     color_iters = 0
     for K in Ks:
@@ -213,6 +266,8 @@ def main():
                              evals_per_color_first=float(ev[0] / n_unique),
                              evals_per_color_last=float(ev[-1] / n_unique))
     value = color_iters / (ms_step * 1e-3)
+    if graph_leg is not None:
+        graph_leg["value"] = color_iters / (graph_leg["ms_per_step"] * 1e-3)
 
     # ---- per-phase times and the full-search comparators (separate passes)
     def timed(fn, reps=5):
@@ -301,13 +356,28 @@ def main():
                     traffic_unit="bytes per launch", avg_launch_us=dur_ms * 1e3,
                     launches=len(launches), bytes_per_launch=bytes_per_launch)
 
+    small = None
+    small_np = synth.workload_image("small", 0)
+    if not args.no_small:
+        small = bench_small(torch, wsm, synth, small_np)
+
     large = None
+    large_np = None
+    if not args.no_large or not args.no_k_sweep:
+        large_np = synth.workload_image("large", 0)
     if not args.no_large:
-        large = bench_large(args, torch, wsm, synth)
+        large = bench_large(args, torch, wsm, synth, large_np)
+
+    sweep = None
+    if not args.no_k_sweep:
+        sweep = k_sweep(torch, wsm, synth, {"512x512": img_np, "4096x4096": large_np}, args.seed)
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, img_np, Ks, n_unique)
+    oracle_t = None
+    if not args.no_oracle_timings:
+        oracle_t = oracle_timings(small_np, large_np)
 
     line = {
         "metric": "WSM color-iterations/s and images/s vs full-search GPU k-means at equal MSE",
@@ -320,6 +390,8 @@ def main():
         "ms_per_step_wall": ms_step_wall,
         "ms_per_step_p10_p50_p90": [float(np.percentile(step_ms, q)) for q in (10, 50, 90)],
         "images_per_s": len(Ks) / (ms_step * 1e-3),
+        "launches": "direct (no graph replay)",
+        "graph_replay": graph_leg,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -334,16 +406,140 @@ def main():
         "comparators": comparators,
         "roofline": roofline,
         "roofline_large": large,
+        "small_256x256": small,
+        "k_scaling": sweep,
         "cpu_baseline": cpu,
+        "oracle_timings": oracle_t,
     }
     print(json.dumps(line), flush=True)
 
 
-def bench_large(args, torch, wsm, synth):
+def _timed(torch, fn, reps=5):
+    """Average ms of fn() over reps calls, events on the current stream,
+    after one untimed call."""
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def _whole_image(torch, wsm, synth, img, K, max_iters, eps, seed=0):
+    """One image through the whole path (reduce, palette, init, iterate,
+    map with MSE), launches direct; returns a callable and a holder of the
+    last state and MSE."""
+    dev = img.device
+    N = img.numel() // 3
+    colors = torch.empty(min(N, 1 << 24), dtype=torch.int32, device=dev)
+    counts = torch.empty_like(colors)
+    nu = torch.empty(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(wsm.reduce_workspace_bytes(N), dtype=torch.uint8, device=dev)
+    lut = torch.empty(1 << 24, dtype=torch.uint8, device=dev)
+    held = {}
+
+    def run():
+        wsm.reduce_colors_into(img, colors, counts, nu, ws)
+        n_u = int(nu.item())
+        col, cnt = colors[:n_u], counts[:n_u]
+        pal = wsm.palette_from_indices(col, synth.init_indices(seed, n_u, K))
+        st = wsm.init(col, cnt, N, pal, reuse=held.get("st"))
+        st.iterate(max_iters, eps)
+        _, _, mse = wsm.map_pixels(st, img, lut=lut)
+        held.update(st=st, mse=mse, n_unique=n_u)
+
+    return run, held
+
+
+def bench_small(torch, wsm, synth, img_np, K=32):
+    """The 256x256 workload (K = 32): the whole image through WSM-C (eps
+    1e-4, at most 50 iterations) and through the fixed 10-iteration variant,
+    and the iterations alone."""
+    img = torch.from_numpy(img_np).to("cuda:0")
+    N = img_np.shape[0] * img_np.shape[1]
+    out = dict(workload="256x256 gradient + blob image (seed 0), K=32", n_pixels=N)
+    for name, (mi, eps) in (("wsm_c", (MAX_ITERS, EPS)), ("fixed10", (10, 0.0))):
+        run, held = _whole_image(torch, wsm, synth, img, K, mi, eps)
+        ms = _timed(torch, run, reps=20)
+        st = held["st"]
+        info = st.info()
+        col, cnt = st.refs[0], st.refs[1]
+        pal = st.refs[2]
+        hold = {}
+
+        def it_only():
+            s_ = wsm.init(col, cnt, N, pal, reuse=hold.get("s"))
+            hold["s"] = s_
+            s_.iterate(mi, eps)
+
+        ms_it = _timed(torch, it_only, reps=20)
+        mse = float(held["mse"].item())
+        out[name] = dict(ms_per_image=ms, images_per_s=1e3 / ms, iterate_ms=ms_it,
+                         iters=info["iters"], converged=info["converged"],
+                         n_unique=held["n_unique"], mse=mse,
+                         psnr_db=10.0 * math.log10(255.0 ** 2 / mse) if mse > 0 else None,
+                         color_iters_per_s=held["n_unique"] * info["iters"] / (ms_it * 1e-3))
+    return out
+
+
+def k_sweep(torch, wsm, synth, images, seed=0, Ks=(2, 4, 8, 16, 32, 64, 128, 256)):
+    """Time and distance evaluations per iteration against K: sort-means and
+    the full search, 10 fixed iterations each, and WSM-C (eps 1e-4, at most
+    50 iterations), from the same seeded palette; launches direct."""
+    out = {}
+    for name, img_np in images.items():
+        if img_np is None:
+            continue
+        img = torch.from_numpy(img_np).to("cuda:0")
+        N = img_np.shape[0] * img_np.shape[1]
+        col, cnt = wsm.reduce_colors(img)
+        n = col.numel()
+        rows = []
+        for K in Ks:
+            pal = wsm.palette_from_indices(col, synth.init_indices(seed, n, K))
+            hold = {}
+
+            def mk(full, mi, eps, pal=pal, hold=hold):
+                def f():
+                    s_ = wsm.init(col, cnt, N, pal, reuse=hold.get((full, mi)))
+                    hold[(full, mi)] = s_
+                    if full:
+                        s_.iterate_full(mi, eps)
+                    else:
+                        s_.iterate(mi, eps)
+                return f
+
+            t_sm = _timed(torch, mk(False, 10, 0.0))
+            t_full = _timed(torch, mk(True, 10, 0.0))
+            t_c = _timed(torch, mk(False, MAX_ITERS, EPS))
+            sm10 = hold[(False, 10)]
+            _, ev = sm10.history()
+            st_c = hold[(False, MAX_ITERS)]
+            it_c = st_c.info()["iters"]
+            sse_c, ev_c = st_c.history()
+            same = bool(torch.equal(sm10.palette64().cpu(), hold[(True, 10)].palette64().cpu()))
+            rows.append(dict(
+                K=K, fixed10_us_per_iter=t_sm * 100.0, full10_us_per_iter=t_full * 100.0,
+                speedup_vs_full=t_full / t_sm,
+                evals_per_color_iter1=float(ev[0] / n),
+                evals_per_color_iters2to10=float(ev[1:].mean() / n) if len(ev) > 1 else None,
+                wsm_c_iters=it_c, wsm_c_ms=t_c, wsm_c_us_per_iter=t_c * 1e3 / it_c,
+                wsm_c_converged=st_c.info()["converged"],
+                wsm_c_evals_per_color_iter=float(ev_c.mean() / n),
+                equal_palette_full=same))
+        out[name] = dict(n_unique=n, rows=rows)
+    return out
+
+
+def bench_large(args, torch, wsm, synth, img_np):
     """Reduction and pixel map on the 4096x4096 workload (~2M unique colors,
-    K = 256), each kernel timed per launch with events on its stream."""
+    K = 256), each kernel timed per launch with events on its stream; and
+    the whole image through WSM-C and through 10 fixed iterations."""
     dev = torch.device("cuda:0")
-    img_np = synth.workload_image("large", 0)
     N = img_np.shape[0] * img_np.shape[1]
     img = torch.from_numpy(img_np).to(dev)
     colors = torch.empty(min(N, 1 << 24), dtype=torch.int32, device=dev)
@@ -422,6 +618,50 @@ def bench_large(args, torch, wsm, synth):
     )
     sse, ev = st.history()
     out["evals_per_color_per_iter"] = [float(e / n_unique) for e in ev]
+    for name, (mi, eps) in (("whole_image_wsm_c", (MAX_ITERS, EPS)), ("whole_image_fixed10", (10, 0.0))):
+        run, held = _whole_image(torch, wsm, synth, img, 256, mi, eps)
+        ms = _timed(torch, run, reps=3)
+        info = held["st"].info()
+        out[name] = dict(ms_per_image=ms, images_per_s=1e3 / ms, iters=info["iters"],
+                         converged=info["converged"], mse=float(held["mse"].item()),
+                         color_iters_per_s=held["n_unique"] * info["iters"] / (ms * 1e-3))
+    return out
+
+
+def oracle_timings(small_np, large_np):
+    """The FP64 oracle (plain C, one thread) on whole images: 100 runs of the
+    256x256 workload (K = 32, WSM-C and 10 fixed iterations) and one run of
+    the 4096x4096 workload (K = 256, 10 fixed iterations; its pixel map is a
+    full search per pixel)."""
+    import oracle
+    import synth
+
+    out = {}
+    N = small_np.shape[0] * small_np.shape[1]
+    for name, (mi, eps) in (("small_wsm_c", (MAX_ITERS, EPS)), ("small_fixed10", (10, 0.0))):
+        t0 = time.perf_counter()
+        runs = 100
+        for _ in range(runs):
+            col, cnt = oracle.reduce_colors(small_np)
+            pal = synth.unpack_keys_to_palette(col[synth.init_indices(0, len(col), 32)])
+            r = oracle.wsm(col, cnt, N, pal, mi, eps)
+            oracle.map_pixels(small_np, col, r["m"], r["centers"])
+        dt = (time.perf_counter() - t0) / runs
+        out[name] = dict(ms_per_image=dt * 1e3, runs=runs, iters=r["iters"])
+    if large_np is not None:
+        NL = large_np.shape[0] * large_np.shape[1]
+        t0 = time.perf_counter()
+        col, cnt = oracle.reduce_colors(large_np)
+        t1 = time.perf_counter()
+        pal = synth.unpack_keys_to_palette(col[synth.init_indices(0, len(col), 256)])
+        r = oracle.wsm(col, cnt, NL, pal, 10, 0.0)
+        t2 = time.perf_counter()
+        oracle.map_pixels(large_np, col, r["m"], r["centers"])
+        t3 = time.perf_counter()
+        out["large_fixed10"] = dict(s_per_image=t3 - t0, reduce_s=t1 - t0, iterate_s=t2 - t1,
+                                    map_s=t3 - t2, runs=1, iters=r["iters"],
+                                    color_iters_per_s=len(col) * r["iters"] / (t2 - t1))
+    out["cores"] = 1
     return out
 
 

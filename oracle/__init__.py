@@ -89,6 +89,10 @@ def _bind(lib):
     lib.oracle_assign_colors.restype = dbl
     lib.oracle_map.argtypes = [P, i64, P, i64, P, P, i32, P, P]
     lib.oracle_map.restype = i32
+    lib.oracle_distortion.argtypes = [P, i64, P, P, i32]
+    lib.oracle_distortion.restype = dbl
+    lib.oracle_distortion_grad.argtypes = [P, i64, P, P, i32, dbl, P, P]
+    lib.oracle_distortion_grad.restype = None
     return lib
 
 
@@ -250,3 +254,26 @@ def map_pixels(rgb, colors, m, centers):
 def psnr(mse: float) -> float:
     """PSNR of Sec. 3.1: 20 log10(255 / sqrt(MSE))."""
     return float(20.0 * np.log10(255.0 / np.sqrt(mse))) if mse > 0 else float("inf")
+
+
+def distortion(x, m, centers):
+    """D = (1/N) sum_p ||x_p - c_{m(p)}||^2 with the assignment m frozen
+    (Eq. 1 over pixels); x [n,3] and centers [K,3] as float64."""
+    lib = _load()
+    x = _c(x, np.float64).reshape(-1, 3)
+    m = _c(m, np.uint8).reshape(-1)
+    c = _c(centers, np.float64)
+    return float(lib.oracle_distortion(_ptr(x), x.shape[0], _ptr(m), _ptr(c), c.shape[0]))
+
+
+def distortion_grad(x, m, centers, g=1.0):
+    """(dD/dx [n,3], dD/dc [K,3]) of distortion(), scaled by g."""
+    lib = _load()
+    x = _c(x, np.float64).reshape(-1, 3)
+    m = _c(m, np.uint8).reshape(-1)
+    c = _c(centers, np.float64)
+    gx = np.empty_like(x)
+    gc = np.empty_like(c)
+    lib.oracle_distortion_grad(_ptr(x), x.shape[0], _ptr(m), _ptr(c), c.shape[0], float(g),
+                               _ptr(gx), _ptr(gc))
+    return gx, gc

@@ -413,3 +413,40 @@ int oracle_map(const uint8_t *rgb, int64_t n_pixels, const uint32_t *colors,
         *mse_out = s / (double)n_pixels;
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Differentiable form of the distortion of Eq. 1 (the weighted SSE of a
+ * quantization, here over the pixels themselves): with the assignment m
+ * frozen,
+ *     D(x, c) = (1/N) sum_p ||x_p - c_{m(p)}||^2,
+ * a quadratic in the pixel colors x and the palette c, whose derivatives are
+ *     dD/dx_p = (2/N) (x_p - c_{m(p)}),
+ *     dD/dc_k = (2/N) sum_{p : m(p) = k} (c_k - x_p).
+ * x is [n][3] and c [K][3], both double; grad_x and grad_c are scaled by
+ * the incoming derivative g = dL/dD. */
+double oracle_distortion(const double *x, int64_t n, const uint8_t *m,
+                         const double *c, int K)
+{
+    (void)K;
+    double s = 0.0;
+    for (int64_t p = 0; p < n; ++p)
+        s += sq_dist(&x[3 * p], &c[3 * m[p]]);
+    return s / (double)n;
+}
+
+void oracle_distortion_grad(const double *x, int64_t n, const uint8_t *m,
+                            const double *c, int K, double g,
+                            double *grad_x, double *grad_c)
+{
+    double scale = 2.0 * g / (double)n;
+    for (int k = 0; k < 3 * K; ++k)
+        grad_c[k] = 0.0;
+    for (int64_t p = 0; p < n; ++p) {
+        int k = m[p];
+        for (int ch = 0; ch < 3; ++ch) {
+            double diff = x[3 * p + ch] - c[3 * k + ch];
+            grad_x[3 * p + ch] = scale * diff;
+            grad_c[3 * k + ch] -= scale * diff;
+        }
+    }
+}

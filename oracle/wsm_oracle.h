@@ -57,6 +57,14 @@ int oracle_map(const uint8_t *rgb, int64_t n_pixels, const uint32_t *colors,
                int64_t n_unique, const uint8_t *m, const double *c, int K,
                uint8_t *idx, double *mse_out);
 
+/* Distortion of Eq. 1 over pixels x[n][3] with frozen assignment m, and its
+ * gradients (scaled by g) with respect to x and the palette c[K][3]. */
+double oracle_distortion(const double *x, int64_t n, const uint8_t *m,
+                         const double *c, int K);
+void oracle_distortion_grad(const double *x, int64_t n, const uint8_t *m,
+                            const double *c, int K, double g,
+                            double *grad_x, double *grad_c);
+
 #ifdef __cplusplus
 }
 #endif

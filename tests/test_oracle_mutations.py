@@ -37,6 +37,12 @@ MUTATIONS = [
      "for (int j = 2; j < K; ++j) {\n            int t = M[(size_t)p * K + j];"),
     ("sse_unweighted", "s += ((double)counts[i] / (double)n_pixels) * min_dist[i];",
      "s += (1.0 / (double)n) * min_dist[i];"),
+    ("grad_factor_two_dropped", "double scale = 2.0 * g / (double)n;", "double scale = g / (double)n;"),
+    ("grad_sign_flipped", "double diff = x[3 * p + ch] - c[3 * k + ch];",
+     "double diff = c[3 * k + ch] - x[3 * p + ch];"),
+    ("grad_palette_sign", "grad_c[3 * k + ch] -= scale * diff;", "grad_c[3 * k + ch] += scale * diff;"),
+    ("distortion_not_averaged", "    return s / (double)n;\n}\n\nvoid oracle_distortion_grad",
+     "    return s;\n}\n\nvoid oracle_distortion_grad"),
 ]
 
 
@@ -54,6 +60,10 @@ def _pin_suite():
     pins.test_empty_cluster_keeps_its_center()
     pins.test_k1_is_mean_color_and_total_variance()
     pins.test_sq_distance_uses_all_three_channels()
+    for seed in range(3):
+        pins.test_distortion_gradient_equals_exact_central_difference(seed)
+    pins.test_distortion_gradient_vanishes_at_exact_centroids()
+    pins.test_distortion_at_nearest_assignment_is_the_map_mse()
 
 
 def test_unmutated_oracle_passes_the_suite():

@@ -304,3 +304,68 @@ def test_sq_distance_uses_all_three_channels():
     d, M = oracle.center_tables(np.array([[0, 0, 0], [1, 2, 2], [0, 0, 1]], float))
     assert d.tolist() == [[0, 9, 1], [9, 0, 6], [1, 6, 0]]
     assert M.tolist() == [[0, 2, 1], [1, 2, 0], [2, 0, 1]]
+
+
+# ---------------------------------------------------------------------------
+# Differentiable form: the distortion of Eq. 1 with frozen assignments and
+# its gradients.  D is a quadratic in x and c, so a central difference in
+# exact rational arithmetic equals the derivative exactly, for any step.
+
+def _exact_distortion(x, m, c):
+    n = len(x)
+    return sum(sqd(x[p], c[m[p]]) for p in range(n)) / n
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_distortion_gradient_equals_exact_central_difference(seed):
+    rng = np.random.default_rng(100 + seed)
+    n, K = int(rng.integers(5, 30)), int(rng.integers(1, 6))
+    x = rng.integers(0, 256, size=(n, 3)).astype(float) + rng.integers(0, 4, size=(n, 3)) / 4
+    c = rng.integers(0, 256, size=(K, 3)).astype(float) + rng.integers(0, 8, size=(K, 3)) / 8
+    m = rng.integers(0, K, size=n).astype(np.uint8)
+    g = 0.75
+    xq = [[Fraction(v) for v in row] for row in x]
+    cq = [[Fraction(v) for v in row] for row in c]
+    D = oracle.distortion(x, m, c)
+    assert D == pytest.approx(float(_exact_distortion(xq, m, cq)), rel=1e-14)
+    gx, gc = oracle.distortion_grad(x, m, c, g)
+    h = Fraction(1, 1000)
+    for (arr, grad, idx) in ((xq, gx, rng.integers(0, n, 4)), (cq, gc, rng.integers(0, K, 3))):
+        for i in idx:
+            for ch in range(3):
+                orig = arr[i][ch]
+                arr[i][ch] = orig + h
+                up = _exact_distortion(xq, m, cq)
+                arr[i][ch] = orig - h
+                dn = _exact_distortion(xq, m, cq)
+                arr[i][ch] = orig
+                fd = Fraction(g) * (up - dn) / (2 * h)
+                assert grad[i, ch] == pytest.approx(float(fd), rel=1e-12, abs=1e-12)
+
+
+def test_distortion_gradient_vanishes_at_exact_centroids():
+    """dD/dc_k is (2/N)(W_k c_k - S_k): zero when every center is the mean
+    of its points (here exact in binary), and the per-cluster sums of dD/dx
+    are minus dD/dc."""
+    rng = np.random.default_rng(7)
+    K = 5
+    m = np.repeat(np.arange(K), 8).astype(np.uint8)
+    x = rng.integers(0, 256, size=(len(m), 3)).astype(float)
+    c = np.stack([x[m == k].mean(0) for k in range(K)])
+    gx, gc = oracle.distortion_grad(x, m, c, 1.0)
+    assert np.abs(gc).max() < 1e-12
+    c2 = c + rng.uniform(-3, 3, size=c.shape)
+    gx, gc = oracle.distortion_grad(x, m, c2, 1.0)
+    for k in range(K):
+        np.testing.assert_allclose(gx[m == k].sum(0), -gc[k], rtol=1e-12, atol=1e-12)
+
+
+def test_distortion_at_nearest_assignment_is_the_map_mse():
+    """With every pixel assigned to its nearest center, D is the pixel MSE
+    that oracle_map reports (Sec. 3.1)."""
+    img = synth.workload_image("small", 1)[:64, :64]
+    col, cnt = oracle.reduce_colors(img)
+    c = synth.unpack_keys_to_palette(col[synth.init_indices(1, len(col), 12)]).astype(float) + 0.3
+    idx, mse = oracle.map_pixels(img, col, np.zeros(len(col), np.uint8), c)
+    D = oracle.distortion(img.reshape(-1, 3).astype(float), idx, c)
+    assert D == pytest.approx(mse, rel=1e-12)
