@@ -116,6 +116,7 @@ def parse():
     ap.add_argument("--no-k-sweep", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-oracle-timings", action="store_true")
+    ap.add_argument("--no-differentiable", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -372,6 +373,10 @@ def main():
     if not args.no_k_sweep:
         sweep = k_sweep(torch, wsm, synth, {"512x512": img_np, "4096x4096": large_np}, args.seed)
 
+    diff = None
+    if not args.no_differentiable:
+        diff = bench_differentiable(torch, wsm, synth)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, img_np, Ks, n_unique)
@@ -408,6 +413,7 @@ def main():
         "roofline_large": large,
         "small_256x256": small,
         "k_scaling": sweep,
+        "differentiable": diff,
         "cpu_baseline": cpu,
         "oracle_timings": oracle_t,
     }
@@ -533,6 +539,48 @@ def k_sweep(torch, wsm, synth, images, seed=0, Ks=(2, 4, 8, 16, 32, 64, 128, 256
                 equal_palette_full=same))
         out[name] = dict(n_unique=n, rows=rows)
     return out
+
+
+def bench_differentiable(torch, wsm, synth, B=16, size=512, K=64):
+    """The differentiable configuration: 16 float32 512x512 images (the
+    sinusoid-field generator), K = 64.  Forward: WSM on each image to the
+    Sec. 3.2 stop (eps 1e-4, at most 50 iterations), then the distortion of
+    Eq. 1 with the map's assignment frozen; backward: its adjoint for the
+    pixels and the palettes.  The adjoint kernels are timed against torch
+    autograd of the same expression (gather, square, mean)."""
+    x = torch.from_numpy(np.stack([synth.sinusoid_field_image(s, size, size)
+                                   for s in range(B)]).astype(np.float32)).to("cuda:0")
+    fn = lambda n, k: synth.init_indices(0, n, k)  # noqa: E731
+    t_fwd = _timed(torch, lambda: wsm.quantize_batch(x, K, fn), reps=2)
+    pal, idx, _ = wsm.quantize_batch(x, K, fn)
+    xf = x.reshape(B, -1, 3)
+
+    def ours():
+        xr = xf.detach().requires_grad_(True)
+        pr = pal.detach().requires_grad_(True)
+        wsm.distortion(xr, pr, idx).sum().backward()
+        return xr.grad, pr.grad
+
+    def plain():
+        xr = xf.detach().requires_grad_(True)
+        pr = pal.detach().requires_grad_(True)
+        c = torch.gather(pr, 1, idx.long()[..., None].expand(-1, -1, 3))
+        ((xr - c) ** 2).sum(-1).mean(-1).sum().backward()
+        return xr.grad, pr.grad
+
+    t_ours = _timed(torch, ours, reps=10)
+    t_plain = _timed(torch, plain, reps=10)
+    gx, gc = ours()
+    px, pc = plain()
+    n_pix = size * size
+    return dict(workload=f"{B} x {size}x{size} float32 sinusoid-field images, K={K}",
+                forward_wsm_ms=t_fwd, adjoint_fwd_bwd_ms=t_ours, torch_autograd_fwd_bwd_ms=t_plain,
+                speedup_vs_torch=t_plain / t_ours,
+                bytes_fwd_bwd=float(B * n_pix * (13 + 13 + 12)),
+                achieved_gbs=B * n_pix * (13 + 13 + 12) / (t_ours * 1e-3) / 1e9,
+                max_rel_diff_grad_x=float(((gx - px).abs().max() / px.abs().max()).item()),
+                max_rel_diff_grad_palette=float(((gc - pc).abs().max() / pc.abs().max()).item()),
+                images_per_s_forward_backward=B / ((t_fwd + t_ours) * 1e-3))
 
 
 def bench_large(args, torch, wsm, synth, img_np):

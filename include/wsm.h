@@ -195,6 +195,36 @@ int wsm_map_pixels(const wsm_problem *prob, const uint8_t *rgb,
                    uint8_t *rgb_out, double *mse_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------ */
+/* Differentiable form (for training systems; the quantization itself is
+ * not differentiated).  The distortion of Eq. 1, taken over the pixels with
+ * the assignment m frozen (the pixel map's indices), for a batch of images:
+ *     D_i = (1/N) sum_p ||x_ip - c_{i,m(p)}||^2,
+ * and its adjoint dD/dx_ip = (2/N)(x_ip - c_{i,m(p)}) and
+ * dD/dc_ik = (2/N) sum_{m(p)=k} (c_ik - x_ip).  D is piecewise quadratic;
+ * away from assignment ties these are its derivatives.
+ *   x:       float [batch][n_pixels][3], pixel colors (any real values)
+ *   index:   uint8 [batch][n_pixels], each < k (larger values read an
+ *            unspecified palette slot, never memory outside the call)
+ *   palette: float [batch][k][3]
+ * Sums are taken in float64; block partials go to workspace (at least
+ * wsm_distortion_workspace_bytes, 16-byte aligned) and are added in a fixed
+ * order.  x, palette and the float outputs must be 4-byte aligned. */
+int wsm_distortion_workspace_bytes(int batch, int64_t n_pixels, int k,
+                                   size_t *bytes /* host */);
+/* d_out: device double [batch]. */
+int wsm_distortion(const float *x, const uint8_t *index, const float *palette,
+                   int batch, int64_t n_pixels, int k, double *d_out,
+                   void *workspace, size_t workspace_bytes, hipStream_t stream);
+/* grad_d: device double [batch], dL/dD_i.  grad_x (float [batch][n][3]) and
+ * grad_palette (float [batch][k][3]) are written when not NULL (at least
+ * one must be given). */
+int wsm_distortion_backward(const float *x, const uint8_t *index,
+                            const float *palette, int batch, int64_t n_pixels,
+                            int k, const double *grad_d, float *grad_x,
+                            float *grad_palette, void *workspace,
+                            size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
 /* Launch replay (not part of the method).  wsm_iterate and
  * wsm_iterate_full enqueue a fixed sequence of kernel launches that depends
  * only on their arguments, and they can be captured into a HIP graph by the

@@ -22,7 +22,7 @@ import torch  # imported before the library so both share one HIP runtime
 __all__ = [
     "WsmError", "library_path", "reduce_colors", "reduce_colors_into",
     "State", "IterateGraph", "init", "init_pixels", "map_pixels", "palette_from_indices",
-    "quantize", "MAX_K", "HISTORY",
+    "quantize", "distortion", "quantize_batch", "MAX_K", "HISTORY",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -93,6 +93,9 @@ def _load():
     lib.wsm_timing_read.argtypes = [ctypes.POINTER(ctypes.c_float), I32, ctypes.POINTER(I32)]
     lib.wsm_timing_detach.argtypes = []
     lib.wsm_reduce_colors_static.argtypes = [P, I64, P, P, I64, P, P]
+    lib.wsm_distortion_workspace_bytes.argtypes = [I32, I64, I32, ctypes.POINTER(SZ)]
+    lib.wsm_distortion.argtypes = [P, P, P, I32, I64, I32, P, P, SZ, P]
+    lib.wsm_distortion_backward.argtypes = [P, P, P, I32, I64, I32, P, P, P, P, SZ, P]
     lib.wsm_iterate_graph_create.argtypes = [PP, I32, D, I32, ctypes.POINTER(P)]
     lib.wsm_iterate_graph_launch.argtypes = [P, P]
     lib.wsm_iterate_graph_destroy.argtypes = [P]
@@ -100,7 +103,8 @@ def _load():
               "wsm_init_pixels", "wsm_iterate", "wsm_iterate_full", "wsm_state_views",
               "wsm_map_pixels", "wsm_gather_palette", "wsm_timing_attach", "wsm_timing_read",
               "wsm_timing_detach", "wsm_iterate_graph_create", "wsm_iterate_graph_launch",
-              "wsm_iterate_graph_destroy", "wsm_reduce_colors_static"):
+              "wsm_iterate_graph_destroy", "wsm_reduce_colors_static",
+              "wsm_distortion_workspace_bytes", "wsm_distortion", "wsm_distortion_backward"):
         getattr(lib, f).restype = I32
     return lib
 
@@ -423,3 +427,79 @@ def quantize(img: torch.Tensor, k: int, init_indices_fn, max_iters: int = 50, ep
     st.iterate(max_iters, eps)
     idx, rgb_out, mse = map_pixels(st, img, want_rgb=want_rgb)
     return st, idx, rgb_out, mse
+
+
+# ---------------------------------------------------------------------------
+# Differentiable form: the distortion of Eq. 1 over the pixels with frozen
+# assignments (wsm_distortion / wsm_distortion_backward).
+
+def _distortion_workspace(batch: int, n: int, k: int, device) -> torch.Tensor:
+    out = ctypes.c_size_t(0)
+    _check(_lib.wsm_distortion_workspace_bytes(int(batch), int(n), int(k), ctypes.byref(out)),
+           "wsm_distortion_workspace_bytes")
+    return torch.empty(int(out.value), dtype=torch.uint8, device=device)
+
+
+class _Distortion(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, palette, index):
+        B, N, _ = x.shape
+        K = palette.shape[1]
+        ws = _distortion_workspace(B, N, K, x.device)
+        d = torch.empty(B, dtype=torch.float64, device=x.device)
+        _check(_lib.wsm_distortion(_ptr(x), _ptr(index), _ptr(palette), B, N, K, _ptr(d),
+                                   _ptr(ws), ws.numel(), _stream()), "wsm_distortion")
+        ctx.save_for_backward(x, palette, index)
+        ctx.mark_non_differentiable(index)
+        return d
+
+    @staticmethod
+    def backward(ctx, grad_d):
+        x, palette, index = ctx.saved_tensors
+        B, N, _ = x.shape
+        K = palette.shape[1]
+        need_x, need_c = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        if not (need_x or need_c):
+            return None, None, None
+        g = grad_d.detach().to(torch.float64).contiguous()
+        gx = torch.empty_like(x) if need_x else None
+        gc = torch.empty_like(palette) if need_c else None
+        ws = _distortion_workspace(B, N, K, x.device)
+        _check(_lib.wsm_distortion_backward(_ptr(x), _ptr(index), _ptr(palette), B, N, K, _ptr(g),
+                                            _ptr(gx), _ptr(gc), _ptr(ws), ws.numel(), _stream()),
+               "wsm_distortion_backward")
+        return gx, gc, None
+
+
+def distortion(x: torch.Tensor, palette: torch.Tensor, index: torch.Tensor) -> torch.Tensor:
+    """Per-image distortion D_i = (1/N) sum_p ||x_ip - c_{i,index(p)}||^2
+    (float64 [B]) with the assignment frozen, differentiable in x (float32
+    [B, N, 3] or [B, H, W, 3]) and palette (float32 [B, K, 3]); index is
+    uint8 [B, N] (or [B, H, W]).  Forward and backward run in the library's
+    kernels."""
+    x = _dev(x, torch.float32, "x")
+    palette = _dev(palette, torch.float32, "palette")
+    index = _dev(index, torch.uint8, "index")
+    B = x.shape[0]
+    return _Distortion.apply(x.reshape(B, -1, 3), palette, index.reshape(B, -1))
+
+
+def quantize_batch(x: torch.Tensor, k: int, init_indices_fn, max_iters: int = 50,
+                   eps: float = 1e-4):
+    """Forward pass of the differentiable form for a batch of float32 images
+    (B, H, W, 3) whose values are 8-bit colors: WSM on each image (reduce,
+    init from ``init_indices_fn(n_unique, k)``, iterate, map).  Returns
+    (palette float32 [B, k, 3], index uint8 [B, H*W], states)."""
+    x = _dev(x, torch.float32, "x")
+    B = x.shape[0]
+    u8 = x.round().clamp(0, 255).to(torch.uint8)
+    if not torch.equal(u8.to(torch.float32), x):
+        raise WsmError("quantize_batch: x must hold 8-bit color values")
+    pals, idxs, states = [], [], []
+    for b in range(B):
+        img = u8[b].contiguous()
+        st, idx, _, _ = quantize(img, k, init_indices_fn, max_iters, eps, want_rgb=False)
+        pals.append(st.palette())
+        idxs.append(idx)
+        states.append(st)
+    return torch.stack(pals).contiguous(), torch.stack(idxs).contiguous(), states

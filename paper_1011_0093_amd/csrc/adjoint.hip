@@ -1,0 +1,207 @@
+// Differentiable form of the quantizer's distortion on gfx950: the weighted
+// SSE of Eq. 1 taken over the pixels themselves,
+//     D = (1/N) sum_p ||x_p - c_{m(p)}||^2,
+// for a batch of images with float32 pixel colors x, palettes c and frozen
+// assignments m (the pixel map), and its adjoint
+//     dD/dx_p = (2/N) (x_p - c_{m(p)}),   dD/dc_k = (2/N) sum_{m(p)=k} (c_k - x_p).
+// D is piecewise quadratic in (x, c); away from assignment ties these are
+// its derivatives.
+//
+// Both passes are HBM-bound streams over the pixels (12 B of color and 1 B
+// of index in; 12 B of gradient out for the adjoint).  Each block takes a
+// tile of kAdjTile pixels of one image and keeps its image's palette in
+// LDS; differences and sums are in float64 (the difference of two float32
+// values is exact in float64).  Per-block partials go to the workspace and
+// are summed in a fixed order by a second launch, so D is reproducible; the
+// palette gradient's per-block sums use LDS float64 atomics.
+#include "sm_block.h"
+
+namespace wsm {
+
+constexpr int kAdjThreads = 256;
+constexpr int kAdjPpt = 16;                         // pixels per thread
+constexpr int kAdjTile = kAdjThreads * kAdjPpt;     // pixels per block
+
+struct AdjLayout {
+    int64_t tiles;          // blocks per image
+    size_t off_d, off_c, bytes;
+};
+
+static AdjLayout adj_layout(int batch, int64_t n, int k) {
+    AdjLayout L;
+    L.tiles = (n + kAdjTile - 1) / kAdjTile;
+    L.off_d = 0;
+    L.off_c = align_up((size_t)batch * L.tiles * 8, 256);
+    L.bytes = align_up(L.off_c + (size_t)batch * L.tiles * k * 3 * 8, 256);
+    return L;
+}
+
+__device__ __forceinline__ void load_palette(const float *__restrict__ pal, int k, float4 *cp) {
+    for (int c = threadIdx.x; c < kMaxK; c += kAdjThreads)
+        cp[c] = c < k ? make_float4(pal[3 * c], pal[3 * c + 1], pal[3 * c + 2], 0.f)
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Block b of image i: sum over its pixels of ||x_p - c_m(p)||^2 (float64),
+// reduced in a fixed order (lanes, then waves), into part[i][b].
+__global__ __launch_bounds__(kAdjThreads) void distortion_partial_kernel(
+    const float *__restrict__ x, const uint8_t *__restrict__ idx, const float *__restrict__ pal,
+    int64_t n, int k, int64_t tiles, double *__restrict__ part) {
+    __shared__ float4 cp[kMaxK];
+    __shared__ double scr[kAdjThreads / 64];
+    const int64_t img = blockIdx.y;
+    load_palette(pal + img * k * 3, k, cp);
+    __syncthreads();
+    const float *xi = x + img * n * 3;
+    const uint8_t *mi = idx + img * n;
+    const int64_t p0 = (int64_t)blockIdx.x * kAdjTile;
+    double s = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < kAdjPpt; ++j) {
+        const int64_t p = p0 + j * kAdjThreads + threadIdx.x;
+        if (p < n) {
+            const float4 c = cp[mi[p]];
+            const double dx = (double)xi[3 * p] - (double)c.x;
+            const double dy = (double)xi[3 * p + 1] - (double)c.y;
+            const double dz = (double)xi[3 * p + 2] - (double)c.z;
+            s += dx * dx + dy * dy + dz * dz;
+        }
+    }
+    const double t = block_sum_f64<kAdjThreads>(s, scr);
+    if (threadIdx.x == 0) part[img * tiles + blockIdx.x] = t;
+}
+
+// D of image i: its block partials summed in order, divided by n.
+__global__ __launch_bounds__(64) void distortion_reduce_kernel(const double *__restrict__ part,
+                                                               int64_t tiles, int64_t n,
+                                                               double *__restrict__ d_out) {
+    const int64_t img = blockIdx.x;
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < tiles; b += 64) s += part[img * tiles + b];
+    s = wave_sum_f64(s);
+    if (threadIdx.x == 63) d_out[img] = s / (double)n;
+}
+
+// Adjoint, block b of image i: dD/dx for its pixels (when grad_x is not
+// null) and the sums over its pixels of x_p - c_m(p) per center, into
+// part[i][b][k][3] (when the palette gradient is wanted).
+__global__ __launch_bounds__(kAdjThreads) void distortion_grad_kernel(
+    const float *__restrict__ x, const uint8_t *__restrict__ idx, const float *__restrict__ pal,
+    int64_t n, int k, int64_t tiles, const double *__restrict__ grad_d, float *__restrict__ grad_x,
+    double *__restrict__ part) {
+    __shared__ float4 cp[kMaxK];
+    __shared__ double acc[kMaxK * 3];
+    const int64_t img = blockIdx.y;
+    load_palette(pal + img * k * 3, k, cp);
+    if (part)
+        for (int c = threadIdx.x; c < k * 3; c += kAdjThreads) acc[c] = 0.0;
+    __syncthreads();
+    const double scale = 2.0 * grad_d[img] / (double)n;
+    const float *xi = x + img * n * 3;
+    const uint8_t *mi = idx + img * n;
+    float *gxi = grad_x ? grad_x + img * n * 3 : nullptr;
+    const int64_t p0 = (int64_t)blockIdx.x * kAdjTile;
+#pragma unroll 4
+    for (int j = 0; j < kAdjPpt; ++j) {
+        const int64_t p = p0 + j * kAdjThreads + threadIdx.x;
+        if (p < n) {
+            const int m = mi[p];
+            const float4 c = cp[m];
+            const double dx = (double)xi[3 * p] - (double)c.x;
+            const double dy = (double)xi[3 * p + 1] - (double)c.y;
+            const double dz = (double)xi[3 * p + 2] - (double)c.z;
+            if (gxi) {
+                gxi[3 * p] = (float)(scale * dx);
+                gxi[3 * p + 1] = (float)(scale * dy);
+                gxi[3 * p + 2] = (float)(scale * dz);
+            }
+            if (part) {
+                atomicAdd(&acc[3 * m], dx);
+                atomicAdd(&acc[3 * m + 1], dy);
+                atomicAdd(&acc[3 * m + 2], dz);
+            }
+        }
+    }
+    if (part) {
+        __syncthreads();
+        double *dst = part + (img * tiles + blockIdx.x) * k * 3;
+        for (int c = threadIdx.x; c < k * 3; c += kAdjThreads) dst[c] = acc[c];
+    }
+}
+
+// dD/dc of image i: for each (center, channel), the block sums added in
+// block order, times -2 g / n.
+__global__ __launch_bounds__(kAdjThreads) void grad_palette_reduce_kernel(
+    const double *__restrict__ part, int64_t tiles, int64_t n, int k,
+    const double *__restrict__ grad_d, float *__restrict__ grad_pal) {
+    const int64_t img = blockIdx.y;
+    const int e = blockIdx.x * kAdjThreads + threadIdx.x;  // center * 3 + channel
+    if (e >= k * 3) return;
+    double s = 0.0;
+    for (int64_t b = 0; b < tiles; ++b) s += part[(img * tiles + b) * k * 3 + e];
+    grad_pal[img * k * 3 + e] = (float)(-2.0 * grad_d[img] / (double)n * s);
+}
+
+}  // namespace wsm
+
+using namespace wsm;
+
+static int adj_check(const float *x, const uint8_t *index, const float *palette, int batch,
+                     int64_t n_pixels, int k, void *workspace, size_t workspace_bytes) {
+    if (!x || !index || !palette || !workspace) return WSM_EINVAL;
+    if (batch < 1 || batch > 65535 || n_pixels < 1 || k < 1 || k > kMaxK) return WSM_EINVAL;
+    if (n_pixels > (int64_t)0xFFFFFFFFll) return WSM_EINVAL;
+    if (((uintptr_t)x & 3u) != 0u || ((uintptr_t)palette & 3u) != 0u) return WSM_EINVAL;
+    if (((uintptr_t)workspace & 15u) != 0u) return WSM_EINVAL;
+    if (workspace_bytes < adj_layout(batch, n_pixels, k).bytes) return WSM_ENOSPC;
+    return WSM_OK;
+}
+
+extern "C" int wsm_distortion_workspace_bytes(int batch, int64_t n_pixels, int k, size_t *bytes) {
+    if (!bytes || batch < 1 || batch > 65535 || n_pixels < 1 || n_pixels > (int64_t)0xFFFFFFFFll ||
+        k < 1 || k > kMaxK)
+        return WSM_EINVAL;
+    *bytes = adj_layout(batch, n_pixels, k).bytes;
+    return WSM_OK;
+}
+
+extern "C" int wsm_distortion(const float *x, const uint8_t *index, const float *palette,
+                              int batch, int64_t n_pixels, int k, double *d_out, void *workspace,
+                              size_t workspace_bytes, hipStream_t stream) {
+    int rc = adj_check(x, index, palette, batch, n_pixels, k, workspace, workspace_bytes);
+    if (rc != WSM_OK) return rc;
+    if (!d_out || ((uintptr_t)d_out & 7u) != 0u) return WSM_EINVAL;
+    const AdjLayout L = adj_layout(batch, n_pixels, k);
+    double *part = (double *)((char *)workspace + L.off_d);
+    (void)hipGetLastError();
+    distortion_partial_kernel<<<dim3((unsigned)L.tiles, (unsigned)batch), dim3(kAdjThreads), 0,
+                                stream>>>(x, index, palette, n_pixels, k, L.tiles, part);
+    distortion_reduce_kernel<<<dim3((unsigned)batch), dim3(64), 0, stream>>>(part, L.tiles,
+                                                                            n_pixels, d_out);
+    return hipGetLastError() == hipSuccess ? WSM_OK : WSM_EHIP;
+}
+
+extern "C" int wsm_distortion_backward(const float *x, const uint8_t *index, const float *palette,
+                                       int batch, int64_t n_pixels, int k, const double *grad_d,
+                                       float *grad_x, float *grad_palette, void *workspace,
+                                       size_t workspace_bytes, hipStream_t stream) {
+    int rc = adj_check(x, index, palette, batch, n_pixels, k, workspace, workspace_bytes);
+    if (rc != WSM_OK) return rc;
+    if (!grad_d || ((uintptr_t)grad_d & 7u) != 0u) return WSM_EINVAL;
+    if (!grad_x && !grad_palette) return WSM_EINVAL;
+    if ((grad_x && ((uintptr_t)grad_x & 3u) != 0u) ||
+        (grad_palette && ((uintptr_t)grad_palette & 3u) != 0u))
+        return WSM_EINVAL;
+    const AdjLayout L = adj_layout(batch, n_pixels, k);
+    double *part = grad_palette ? (double *)((char *)workspace + L.off_c) : nullptr;
+    (void)hipGetLastError();
+    distortion_grad_kernel<<<dim3((unsigned)L.tiles, (unsigned)batch), dim3(kAdjThreads), 0,
+                             stream>>>(x, index, palette, n_pixels, k, L.tiles, grad_d, grad_x,
+                                       part);
+    if (grad_palette)
+        grad_palette_reduce_kernel<<<dim3((unsigned)((k * 3 + kAdjThreads - 1) / kAdjThreads),
+                                          (unsigned)batch),
+                                     dim3(kAdjThreads), 0, stream>>>(part, L.tiles, n_pixels, k,
+                                                                     grad_d, grad_palette);
+    return hipGetLastError() == hipSuccess ? WSM_OK : WSM_EHIP;
+}
