@@ -117,6 +117,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-oracle-timings", action="store_true")
     ap.add_argument("--no-differentiable", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -373,6 +374,10 @@ def main():
     if not args.no_k_sweep:
         sweep = k_sweep(torch, wsm, synth, {"512x512": img_np, "4096x4096": large_np}, args.seed)
 
+    batched = None
+    if not args.no_batched:
+        batched = bench_batched(torch, wsm, synth)
+
     diff = None
     if not args.no_differentiable:
         diff = bench_differentiable(torch, wsm, synth)
@@ -413,6 +418,7 @@ def main():
         "roofline_large": large,
         "small_256x256": small,
         "k_scaling": sweep,
+        "batched": batched,
         "differentiable": diff,
         "cpu_baseline": cpu,
         "oracle_timings": oracle_t,
@@ -539,6 +545,97 @@ def k_sweep(torch, wsm, synth, images, seed=0, Ks=(2, 4, 8, 16, 32, 64, 128, 256
                 equal_palette_full=same))
         out[name] = dict(n_unique=n, rows=rows)
     return out
+
+
+def bench_batched(torch, wsm, synth, n_images=64):
+    """The batched configuration: 64 square images, side uniform in
+    [128, 1024], K drawn from {16, 32, 64, 128, 256} (seeded), each through
+    the whole path (reduce, palette, init, WSM-C at eps 1e-4 with at most 50
+    iterations, map with MSE).  Sequential: 64 plain per-image calls.
+    Batched: the 64 reductions, one read-back of the unique counts, the 64
+    inits, one persistent launch for all the iterations (a plan recorded
+    once for these images), the 64 maps.  Equal MSE is checked image by
+    image (the palettes are bit-identical)."""
+    work = synth.batched_workload(0, n_images)
+    imgs = [torch.from_numpy(img).to("cuda:0") for img, _, _ in work]
+    Ks = [k for _, k, _ in work]
+    seeds = [s for _, _, s in work]
+    lut = torch.empty(1 << 24, dtype=torch.uint8, device="cuda:0")
+    seq_states = {}
+
+    def sequential():
+        out = []
+        for j, (g, K, sd) in enumerate(zip(imgs, Ks, seeds)):
+            col, cnt = wsm.reduce_colors(g)
+            pal = wsm.palette_from_indices(col, synth.init_indices(sd, col.numel(), K))
+            st = wsm.init(col, cnt, g.numel() // 3, pal, reuse=seq_states.get(j))
+            seq_states[j] = st
+            st.iterate(MAX_ITERS, EPS)
+            _, _, mse = wsm.map_pixels(st, g, lut=lut)
+            out.append(mse)
+        return out
+
+    t_seq = _timed(torch, sequential, reps=2)
+    seq_mse = [float(m.item()) for m in sequential()]
+    # batched: fixed buffers per image
+    bufs = []
+    for g in imgs:
+        N = g.numel() // 3
+        bufs.append(dict(
+            colors=torch.empty(min(N, 1 << 24), dtype=torch.int32, device="cuda:0"),
+            counts=torch.empty(min(N, 1 << 24), dtype=torch.int32, device="cuda:0"),
+            nu=torch.empty(1, dtype=torch.int32, device="cuda:0"),
+            ws=torch.empty(wsm.reduce_workspace_bytes(N), dtype=torch.uint8, device="cuda:0"),
+            idx=torch.empty(N, dtype=torch.uint8, device="cuda:0"),
+            mse=torch.empty(1, dtype=torch.float64, device="cuda:0")))
+    holder = {}
+
+    def prepare():
+        for g, b in zip(imgs, bufs):
+            wsm.reduce_colors_into(g, b["colors"], b["counts"], b["nu"], b["ws"])
+        nus = torch.cat([b["nu"] for b in bufs]).cpu().tolist()  # one read-back for all
+        states = holder.get("states")
+        new = []
+        for j, (g, b, K, sd) in enumerate(zip(imgs, bufs, Ks, seeds)):
+            col, cnt = b["colors"][:nus[j]], b["counts"][:nus[j]]
+            pal = wsm.palette_from_indices(col, synth.init_indices(sd, nus[j], K))
+            new.append(wsm.init(col, cnt, g.numel() // 3, pal,
+                                reuse=states[j] if states else None))
+        holder["states"] = new
+        return new
+
+    states = prepare()
+    t0 = time.perf_counter()
+    plan = wsm.Batch(states, MAX_ITERS, EPS)
+    t_plan = (time.perf_counter() - t0) * 1e3
+
+    def batched():
+        st_ = prepare()
+        plan.launch()
+        for g, b, st in zip(imgs, bufs, st_):
+            wsm.map_pixels_into(st, g, lut, b["idx"], b["mse"])
+
+    t_bat = _timed(torch, batched, reps=2)
+    batched()
+    torch.cuda.synchronize()
+    err = plan.error()
+    bat_mse = [float(b["mse"].item()) for b in bufs]
+    same = all(torch.equal(a.palette64().cpu(), seq_states[j].palette64().cpu())
+               for j, a in enumerate(holder["states"]))
+    # the persistent launch alone
+    t_launch = _timed(torch, lambda: (prepare(), plan.launch()), reps=2) - _timed(torch, prepare, reps=2)
+    plan.close()
+    n_pix = sum(g.numel() // 3 for g in imgs)
+    return dict(workload=f"{n_images} images, side U[128,1024] (seeded), K from {{16,32,64,128,256}}, "
+                         "WSM-C eps 1e-4, max 50 iterations, whole path per image",
+                n_images=n_images, n_pixels=n_pix, sequential_ms=t_seq, batched_ms=t_bat,
+                images_per_s_sequential=n_images / (t_seq * 1e-3),
+                images_per_s_batched=n_images / (t_bat * 1e-3), speedup=t_seq / t_bat,
+                persistent_launch_ms_est=t_launch, plan_create_ms=t_plan,
+                images_per_s_batched_with_plan=n_images / ((t_bat + t_plan) * 1e-3),
+                equal_palettes=bool(same),
+                max_rel_mse_diff=max(abs(a - b) / b for a, b in zip(bat_mse, seq_mse)),
+                batch_error_bits=err)
 
 
 def bench_differentiable(torch, wsm, synth, B=16, size=512, K=64):

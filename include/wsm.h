@@ -195,6 +195,41 @@ int wsm_map_pixels(const wsm_problem *prob, const uint8_t *rgb,
                    uint8_t *rgb_out, double *mse_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------ */
+/* Batched persistent form: the iterations of many images (their own
+ * tables, K, iteration budgets and eps), each bound to its own state by
+ * wsm_init, run by one launch of persistent blocks that take work items
+ * from a device queue -- per image and step, the update with the row sort
+ * of M (in parts of rows_per_item rows) and the sort-means search (in grid
+ * virtual blocks).  Each image's result is that of wsm_iterate(max_iters,
+ * eps) on it, bit for bit.
+ *   probs[n_images] (host): initialised COLORS problems on one device, with
+ *     255 * n_pixels < 2^32; at most 128 images.
+ *   max_iters, eps (host, per image): as for wsm_iterate.
+ *   grid, rows_per_item (host, per image, nullable; 0 = default): the work
+ *     split (search blocks, 1..2048, default the problem's grid; rows per
+ *     rows item, default 1), as an autotuner picks them.
+ * wsm_batch_create binds a caller-owned workspace (256-byte aligned, at
+ * least wsm_batch_workspace_bytes) and records the queue reset and the
+ * persistent launch into a HIP graph; it synchronizes the host once (set-up
+ * copies) and the runtime may reserve device memory for the graph.
+ * wsm_batch_launch enqueues a whole run on `stream`; states must have been
+ * re-initialised (wsm_init) if they should start over.  wsm_batch_error
+ * gives a device int32 with error bits of the last run (1: a block gave up
+ * waiting, 2: the queue overflowed; 0 when all is well).  Launches of one
+ * handle must not overlap. */
+typedef struct wsm_batch wsm_batch;
+int wsm_batch_workspace_bytes(int n_images, const wsm_problem *probs,
+                              const int32_t *max_iters, const int32_t *grid,
+                              const int32_t *rows_per_item, size_t *bytes /* host */);
+int wsm_batch_create(int n_images, const wsm_problem *probs, const int32_t *max_iters,
+                     const double *eps, const int32_t *grid,
+                     const int32_t *rows_per_item, void *workspace,
+                     size_t workspace_bytes, wsm_batch **batch /* host, out */);
+int wsm_batch_launch(wsm_batch *batch, hipStream_t stream);
+int wsm_batch_error(const wsm_batch *batch, const int32_t **err /* host, out */);
+int wsm_batch_destroy(wsm_batch *batch);
+
+/* ------------------------------------------------------------------ */
 /* Differentiable form (for training systems; the quantization itself is
  * not differentiated).  The distortion of Eq. 1, taken over the pixels with
  * the assignment m frozen (the pixel map's indices), for a batch of images:

@@ -22,7 +22,7 @@ import torch  # imported before the library so both share one HIP runtime
 __all__ = [
     "WsmError", "library_path", "reduce_colors", "reduce_colors_into",
     "State", "IterateGraph", "init", "init_pixels", "map_pixels", "palette_from_indices",
-    "quantize", "distortion", "quantize_batch", "MAX_K", "HISTORY",
+    "quantize", "distortion", "quantize_batch", "Batch", "MAX_K", "HISTORY",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -96,6 +96,11 @@ def _load():
     lib.wsm_distortion_workspace_bytes.argtypes = [I32, I64, I32, ctypes.POINTER(SZ)]
     lib.wsm_distortion.argtypes = [P, P, P, I32, I64, I32, P, P, SZ, P]
     lib.wsm_distortion_backward.argtypes = [P, P, P, I32, I64, I32, P, P, P, P, SZ, P]
+    lib.wsm_batch_workspace_bytes.argtypes = [I32, PP, P, P, P, ctypes.POINTER(SZ)]
+    lib.wsm_batch_create.argtypes = [I32, PP, P, P, P, P, P, SZ, ctypes.POINTER(P)]
+    lib.wsm_batch_launch.argtypes = [P, P]
+    lib.wsm_batch_error.argtypes = [P, ctypes.POINTER(P)]
+    lib.wsm_batch_destroy.argtypes = [P]
     lib.wsm_iterate_graph_create.argtypes = [PP, I32, D, I32, ctypes.POINTER(P)]
     lib.wsm_iterate_graph_launch.argtypes = [P, P]
     lib.wsm_iterate_graph_destroy.argtypes = [P]
@@ -104,7 +109,9 @@ def _load():
               "wsm_map_pixels", "wsm_gather_palette", "wsm_timing_attach", "wsm_timing_read",
               "wsm_timing_detach", "wsm_iterate_graph_create", "wsm_iterate_graph_launch",
               "wsm_iterate_graph_destroy", "wsm_reduce_colors_static",
-              "wsm_distortion_workspace_bytes", "wsm_distortion", "wsm_distortion_backward"):
+              "wsm_distortion_workspace_bytes", "wsm_distortion", "wsm_distortion_backward",
+              "wsm_batch_workspace_bytes", "wsm_batch_create", "wsm_batch_launch",
+              "wsm_batch_error", "wsm_batch_destroy"):
         getattr(lib, f).restype = I32
     return lib
 
@@ -304,6 +311,68 @@ class IterateGraph:
             pass
 
 
+class Batch:
+    """Batched persistent iterations (wsm_batch_*): one launch iterates every
+    state of the list, each as state.iterate(max_iters[i], eps[i]) would.
+    grid and rows_per_item (per state, 0 = default) split the work; an
+    autotuner picks them.  The plan is recorded once; launch() runs it on
+    the current stream (re-initialise the states with init(..., reuse=)
+    before a launch that should start over)."""
+
+    def __init__(self, states, max_iters, eps, grid=None, rows_per_item=None, tuned=True):
+        n = len(states)
+        self.states = list(states)
+        if tuned and grid is None and rows_per_item is None:
+            from . import autotune
+            table = autotune.load()
+            if table:
+                split = [autotune.split_for(table, st.n_points, st.k) for st in states]
+                grid = [g for g, _ in split]
+                rows_per_item = [r for _, r in split]
+        self._probs = (_Problem * n)(*[st.prob for st in states])
+        as_list = lambda v, t: [t(x) for x in (v if hasattr(v, "__len__") else [v] * n)]  # noqa: E731
+        self._mi = (ctypes.c_int32 * n)(*as_list(max_iters, int))
+        self._eps = (ctypes.c_double * n)(*as_list(eps, float))
+        self._grid = (ctypes.c_int32 * n)(*as_list(grid or 0, int))
+        self._rpi = (ctypes.c_int32 * n)(*as_list(rows_per_item or 0, int))
+        size = ctypes.c_size_t(0)
+        _check(_lib.wsm_batch_workspace_bytes(n, self._probs, self._mi, self._grid, self._rpi,
+                                              ctypes.byref(size)), "wsm_batch_workspace_bytes")
+        dev = states[0].buf.device
+        raw = torch.empty(int(size.value) + 256, dtype=torch.uint8, device=dev)
+        off = (-raw.data_ptr()) % 256
+        self.ws = raw[off:off + int(size.value)]
+        self._raw = raw
+        h = ctypes.c_void_p(0)
+        _check(_lib.wsm_batch_create(n, self._probs, self._mi, self._eps, self._grid, self._rpi,
+                                     _ptr(self.ws), self.ws.numel(), ctypes.byref(h)),
+               "wsm_batch_create")
+        self._h = h
+        e = ctypes.c_void_p(0)
+        _check(_lib.wsm_batch_error(h, ctypes.byref(e)), "wsm_batch_error")
+        self._err_off = e.value - self.ws.data_ptr()
+
+    def launch(self) -> None:
+        if not self._h:
+            raise WsmError("batch already closed")
+        _check(_lib.wsm_batch_launch(self._h, _stream()), "wsm_batch_launch")
+
+    def error(self) -> int:
+        """Error bits of the last run (reads the device; 0 when all is well)."""
+        return int(self.ws[self._err_off:self._err_off + 4].view(torch.int32).item())
+
+    def close(self) -> None:
+        if self._h:
+            _lib.wsm_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def _new_state(n_points: int, k: int, device) -> torch.Tensor:
     nbytes = state_bytes(n_points, k)
     buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
@@ -363,6 +432,14 @@ def map_pixels(state: State, img: torch.Tensor, lut: torch.Tensor | None = None,
     _check(_lib.wsm_map_pixels(ctypes.byref(state.prob), _ptr(img), n, _ptr(lut), _ptr(idx),
                                _ptr(rgb_out), _ptr(mse), _stream()), "wsm_map_pixels")
     return idx, rgb_out, mse
+
+
+def map_pixels_into(state: State, img: torch.Tensor, lut: torch.Tensor, index: torch.Tensor,
+                    mse: torch.Tensor | None = None, rgb_out: torch.Tensor | None = None) -> None:
+    """Asynchronous form of map_pixels with caller-provided outputs."""
+    img = _dev(img, torch.uint8, "img")
+    _check(_lib.wsm_map_pixels(ctypes.byref(state.prob), _ptr(img), img.numel() // 3, _ptr(lut),
+                               _ptr(index), _ptr(rgb_out), _ptr(mse), _stream()), "wsm_map_pixels")
 
 
 def palette_from_indices(colors: torch.Tensor, indices, out: torch.Tensor | None = None

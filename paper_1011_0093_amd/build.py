@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwsm.so")
-SOURCES = ["api.hip", "timing.hip", "reduce.hip", "iterate.hip", "map.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "timing.hip", "reduce.hip", "iterate.hip", "map.hip", "adjoint.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
