@@ -62,11 +62,12 @@ def _time(fn, reps=3):
     return a.elapsed_time(b) / reps
 
 
-def tune(sides=(128, 256, 384, 512, 768, 1024), ks=KS, images_per_class=4, max_iters=10,
+def tune(sides=(128, 256, 512, 768, 1024), ks=KS, images_per_class=16, max_iters=10,
          path: str = CACHE, seed: int = 0, log=print) -> dict:
     """Times every candidate split for each (N' bucket, K) class met by
-    images of the given sides, 10 fixed iterations per image, and writes the
-    winners to `path`."""
+    images of the given sides -- a batch of images_per_class images of the
+    class, enough to fill the GPU as a real batch does, 10 fixed iterations
+    per image -- and writes the winners to `path`."""
     import synth
     table = load(path)
     for side in sides:

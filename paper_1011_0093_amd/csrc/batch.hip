@@ -5,16 +5,19 @@
 //
 // An image's steps are those of the per-image launches (iterate.hip), cut
 // into work items:
-//   rows item (image, r):   the update of the previous step and rows
-//                           r * rpi .. (r + 1) * rpi - 1 of M (rows_body);
+//   start item (image):     the first step's centers published
+//                           (update_body);
+//   rows item (image, r):   rows r * rpi .. (r + 1) * rpi - 1 of M for the
+//                           step's centers (sort_body);
 //   search item (image, v): virtual block v of the image's search grid
 //                           (search_body).
-// The block that completes the last item of a phase enqueues the image's
-// next phase: after the rows, its search items, or -- when the update found
-// the Sec. 3.2 criterion met -- the final update (final_body) and the end of
-// the image; after the search, the next step's rows items, or the final
-// update when the iteration budget is spent.  Images interleave freely, so
-// small images and the short phases of one image fill the GPU together.
+// The block that completes the last item of a phase goes on with the image:
+// after the rows, it enqueues the search items; after the search, it applies
+// the update once (update_body) -- or the final update (final_body) when the
+// iteration budget is spent or the Sec. 3.2 criterion has fired, ending the
+// image -- and enqueues the next step's rows items.  Images interleave
+// freely, so small images and the short phases of one image fill the GPU
+// together.
 //
 // Queue protocol (device memory of the caller's workspace): a block claims
 // the next slot with an atomic on `head` and waits until the slot's ready
@@ -38,6 +41,7 @@ namespace wsm {
 constexpr int kBatchMaxImages = 128;
 constexpr uint32_t kItemRows = 0u;
 constexpr uint32_t kItemSearch = 1u;
+constexpr uint32_t kItemStart = 2u;
 constexpr uint32_t kNoItem = ~0u;
 // longest wait for one slot, in ticks of the constant 100 MHz realtime
 // counter (2 s; a whole batch takes milliseconds)
@@ -71,7 +75,7 @@ struct ImgCtl {
 };
 
 __host__ __device__ constexpr uint32_t make_item(uint32_t image, uint32_t kind, uint32_t index) {
-    return (image << 25) | (kind << 24) | index;
+    return (image << 25) | (kind << 23) | index;
 }
 
 union BatchLds {
@@ -81,8 +85,8 @@ union BatchLds {
     FinalLds<kSearchThreads> f;
 };
 
-// Resets the queue for a launch: the next run number, one rows item per
-// rows part of every image's first step.  One block.
+// Resets the queue for a launch: the next run number, one start item per
+// image.  One block.
 __global__ __launch_bounds__(256) void batch_reset_kernel(const BatchImage *__restrict__ img,
                                                           BatchCtl *ctl, ImgCtl *ictl,
                                                           uint32_t *items, uint32_t *ready) {
@@ -96,20 +100,13 @@ __global__ __launch_bounds__(256) void batch_reset_kernel(const BatchImage *__re
         ctl->err = 0;
     }
     __syncthreads();
-    uint32_t off = 0;
-    for (int i = 0; i < n; ++i) {
-        const int ri = img[i].rows_items;
-        for (int r = threadIdx.x; r < ri; r += blockDim.x) {
-            items[off + r] = make_item((uint32_t)i, kItemRows, (uint32_t)r);
-            ready[off + r] = s_run;
-        }
-        off += (uint32_t)ri;
-        if (threadIdx.x == 0) {
-            ictl[i].step = 0u;
-            ictl[i].done = 0u;
-        }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        items[i] = make_item((uint32_t)i, kItemStart, 0u);
+        ready[i] = s_run;
+        ictl[i].step = 0u;
+        ictl[i].done = 0u;
     }
-    if (threadIdx.x == 0) ctl->tail = off;
+    if (threadIdx.x == 0) ctl->tail = (uint32_t)n;
 }
 
 // Appends n_new items (image, kind, 0..n_new-1) to the queue.  All threads
@@ -171,14 +168,30 @@ __global__ __launch_bounds__(kSearchThreads) void batch_kernel(const BatchImage 
         // the item is the same for the whole block: scalar registers
         const uint32_t item = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_item);
         if (item == kNoItem) return;
-        const uint32_t im = item >> 25, kind = (item >> 24) & 1u, idx = item & 0xFFFFFFu;
+        const uint32_t im = item >> 25, kind = (item >> 23) & 3u, idx = item & 0x7FFFFFu;
         const BatchImage &B = img[im];
         const IterArgs a = B.a;
         const int step = __builtin_amdgcn_readfirstlane((int)ictl[im].step);
+        if (kind == kItemStart) {
+            // the first step's centers (a state that had already converged
+            // is final at once)
+            const Record rec = update_body<kSearchThreads, true>(a, 0, L.f);
+            if (rec.converged) {
+                final_body<kSearchThreads, true>(a, 1, L.f);
+                __syncthreads();
+                if (tid == 0) {
+                    __threadfence();
+                    atomicSub(&ctl->remaining, 1);
+                }
+            } else {
+                enqueue(ctl, items, ready, run, im, kItemRows, (uint32_t)B.rows_items, &s_base);
+            }
+            continue;
+        }
         if (kind == kItemRows) {
             const int p0 = (int)idx * B.rows_per_item;
             const int p1 = p0 + B.rows_per_item < a.k ? p0 + B.rows_per_item : a.k;
-            rows_body<true>(a, step, p0, p1, L.r);
+            sort_body(a, step, p0, p1, L.r);
         } else if (step == 0) {
             search_body<true, false, true>(a, step, (int)idx, L.n);
         } else if (a.k >= kDeferMinK) {
@@ -189,7 +202,7 @@ __global__ __launch_bounds__(kSearchThreads) void batch_kernel(const BatchImage 
         // completion of the item; the last one of the phase goes on
         __syncthreads();
         if (tid == 0) {
-            const uint32_t total = kind == kItemRows ? (uint32_t)B.rows_items : (uint32_t)a.grid;
+            const uint32_t total = kind == kItemRows ? (uint32_t)B.rows_items : (uint32_t)a.grid;  // start items return above
             __threadfence();
             const uint32_t old = atomicAdd(&ictl[im].done, 1u);
             __threadfence();
@@ -204,22 +217,22 @@ __global__ __launch_bounds__(kSearchThreads) void batch_kernel(const BatchImage 
         if (!s_last) continue;
         bool finished = false;
         if (kind == kItemRows) {
-            const Record rec = a.sv.hdr->rec[(step + 1) & 1];
-            if (rec.converged) {
-                final_body<kSearchThreads, true>(a, step + 1, L.f);
-                finished = true;
-            } else {
-                enqueue(ctl, items, ready, run, im, kItemSearch, (uint32_t)a.grid, &s_base);
-            }
+            enqueue(ctl, items, ready, run, im, kItemSearch, (uint32_t)a.grid, &s_base);
         } else if (step + 1 >= B.max_iters) {
             final_body<kSearchThreads, true>(a, step + 1, L.f);
             finished = true;
         } else {
-            if (tid == 0) {
-                ictl[im].step = (uint32_t)(step + 1);
-                __threadfence();
+            const Record rec = update_body<kSearchThreads, true>(a, step + 1, L.f);
+            if (rec.converged) {
+                final_body<kSearchThreads, true>(a, step + 2, L.f);
+                finished = true;
+            } else {
+                if (tid == 0) {
+                    ictl[im].step = (uint32_t)(step + 1);
+                    __threadfence();
+                }
+                enqueue(ctl, items, ready, run, im, kItemRows, (uint32_t)B.rows_items, &s_base);
             }
-            enqueue(ctl, items, ready, run, im, kItemRows, (uint32_t)B.rows_items, &s_base);
         }
         if (finished) {
             __syncthreads();
@@ -286,7 +299,7 @@ static int batch_layout(int n_images, const wsm_problem *probs, const int32_t *m
         const int rpi = rows_per_item && rows_per_item[i] > 0 ? rows_per_item[i] : 1;
         if (rpi > kMaxK) return WSM_EINVAL;
         const int ri = (p.k + rpi - 1) / rpi;
-        items += (uint64_t)max_iters[i] * (uint64_t)(ri + g);
+        items += 1 + (uint64_t)max_iters[i] * (uint64_t)(ri + g);
     }
     // every persistent block claims one slot past the last item when it leaves
     items += 4096;

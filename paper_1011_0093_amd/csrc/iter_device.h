@@ -503,6 +503,31 @@ __device__ void search_body(const IterArgs &a, int i, int vb, SearchLds<DEFER> &
 }
 
 
+// The update of step i-1 alone (one block of NT threads): published, with
+// the record, for step i; unless the stopping rule has fired, the totals
+// slot step i accumulates into is cleared.  Returns the record.
+template <int NT, bool PACKED>
+__device__ Record update_body(const IterArgs &a, int i, FinalLds<NT> &L) {
+    const Record r = update_phase<NT, PACKED>(a, i, L.cen, L.cen64, true, L.dscr, L.uscr);
+    if (!r.converged) {
+        unsigned long long *T = a.sv.totals + (size_t)(i % 3) * kMaxK * 4;
+        for (int c = threadIdx.x; c < kMaxK * 4; c += NT) T[c] = 0ull;
+    }
+    __syncthreads();
+    __threadfence();
+    return r;
+}
+
+// Rows p0 .. p1-1 of M for the centers published for step i (kSortThreads
+// threads).
+__device__ void sort_body(const IterArgs &a, int i, int p0, int p1, RowsLds &L) {
+    const float4 *pal = a.sv.pal + (size_t)((i + 1) & 1) * kMaxK;
+    for (int c = threadIdx.x; c < a.k; c += kSortThreads) L.cen[c] = pal[c];
+    for (int p = p0; p < p1; ++p)  // sort_row starts with a barrier
+        sort_row<kSortThreads>(L.cen, a.k, p, L.keys, L.rank, a.sv.rows + (size_t)p * kRowStride,
+                               a.sv.rowd + (size_t)p * kRowDist);
+}
+
 // Final update after the last step of a call (one block of NT threads).
 // Publishes the palette and record to slot 0 and clears totals[0] for the
 // next call.
