@@ -19,31 +19,59 @@ struct IterArgs {
 };
 
 // Center totals: packed as two u64 (sum cR | sum cG << 32, sum cB | sum c << 32)
-// when 255 * n_pixels < 2^32, else four u64.  The center is the float64
-// quotient of the exact sums (their correctly rounded mean); an empty
-// cluster keeps its center.
+// when 255 * n_pixels < 2^32, else four u64; center c's words are
+// c * NW .. c * NW + NW - 1 (NW = 2 or 4) of each of the kTotCopies copies
+// of a slot.  The center is the float64 quotient of the exact sums (their
+// correctly rounded mean); an empty cluster keeps its center.
 template <bool PACKED>
-__device__ __forceinline__ void totals_to_center(const unsigned long long *T, int c,
-                                                 double4 prev, double4 &out) {
+constexpr int tot_words() { return PACKED ? 2 : 4; }
+
+// Words w < k * NW of the copies of slot T, summed into tot[w] (LDS), one
+// word per thread with the loads of all copies issued together.  Packed
+// words add field by field: no field of a total reaches 2^32, so no carry
+// crosses a field.
+template <int NT, bool PACKED>
+__device__ __forceinline__ void gather_totals(const unsigned long long *T, int k,
+                                              unsigned long long *tot) {
+    for (int w = threadIdx.x; w < k * tot_words<PACKED>(); w += NT) {
+        unsigned long long v[kTotCopies];
+#pragma unroll
+        for (int q = 0; q < kTotCopies; ++q) v[q] = T[q * kTotCopy + w];
+        unsigned long long t = 0ull;
+#pragma unroll
+        for (int q = 0; q < kTotCopies; ++q) t += v[q];
+        tot[w] = t;
+    }
+}
+
+// Zeroes the words of the copies of slot T that k centers use.
+template <int NT, bool PACKED>
+__device__ __forceinline__ void clear_totals(unsigned long long *T, int k) {
+#pragma unroll
+    for (int q = 0; q < kTotCopies; ++q)
+        for (int w = threadIdx.x; w < k * tot_words<PACKED>(); w += NT) T[q * kTotCopy + w] = 0ull;
+}
+
+template <bool PACKED>
+__device__ __forceinline__ double4 totals_to_center(const unsigned long long *tot, int c,
+                                                    double4 prev) {
+    constexpr int NW = tot_words<PACKED>();
     unsigned long long sr, sg, sb, w;
     if (PACKED) {
-        const unsigned long long a = T[c * 4 + 0], b = T[c * 4 + 1];
+        const unsigned long long a = tot[c * NW], b = tot[c * NW + 1];
         sr = a & 0xFFFFFFFFull;
         sg = a >> 32;
         sb = b & 0xFFFFFFFFull;
         w = b >> 32;
     } else {
-        sr = T[c * 4 + 0];
-        sg = T[c * 4 + 1];
-        sb = T[c * 4 + 2];
-        w = T[c * 4 + 3];
+        sr = tot[c * NW];
+        sg = tot[c * NW + 1];
+        sb = tot[c * NW + 2];
+        w = tot[c * NW + 3];
     }
-    if (w != 0ull) {
-        const double dw = (double)w;
-        out = make_double4((double)sr / dw, (double)sg / dw, (double)sb / dw, 0.0);
-    } else {
-        out = prev;  // empty cluster keeps its center
-    }
+    if (w == 0ull) return prev;  // empty cluster keeps its center
+    const double dw = (double)w;
+    return make_double4((double)sr / dw, (double)sg / dw, (double)sb / dw, 0.0);
 }
 
 // Update phase (see the file comment).  Returns the record after the update,
@@ -52,7 +80,8 @@ __device__ __forceinline__ void totals_to_center(const unsigned long long *T, in
 // cen64 if it is not null.
 template <int NT, bool PACKED>
 __device__ Record update_phase(const IterArgs &a, int i, float4 *cen, double4 *cen64,
-                               bool writer, double *dscr, unsigned long long *uscr) {
+                               bool writer, double *dscr, unsigned long long *uscr,
+                               unsigned long long *tot) {
     constexpr int kPer = kMaxK / NT > 0 ? kMaxK / NT : 1;
     const int tid = threadIdx.x;
     const Record rin = a.sv.hdr->rec[i & 1];
@@ -60,20 +89,14 @@ __device__ Record update_phase(const IterArgs &a, int i, float4 *cen, double4 *c
     float4 *pal_out = a.sv.pal + (size_t)((i + 1) & 1) * kMaxK;
     double4 *pal64_out = a.sv.pal64 + (size_t)((i + 1) & 1) * kMaxK;
     const int prv = (i + 2) % 3;  // totals slot of step i-1
-    const unsigned long long *T = a.sv.totals + (size_t)prv * kMaxK * 4;
+    const unsigned long long *T = a.sv.totals + (size_t)prv * kTotSlot;
     // Issue every load first; which values are used is decided afterwards.
     const bool update = (i != 0) && !rin.converged;
     double4 cv[kPer];
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
         const int c = tid + r * NT;
-        cv[r] = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (c < a.k) {
-            const double4 old = pal_in[c];
-            double4 upd;
-            totals_to_center<PACKED>(T, c, old, upd);
-            cv[r] = update ? upd : old;
-        }
+        cv[r] = c < a.k ? pal_in[c] : make_double4(0.0, 0.0, 0.0, 0.0);
     }
     // Lane l of the first wave sums partials l, l + 64, l + 128, ... in that
     // order; the loads of eight of them are issued together.
@@ -98,11 +121,14 @@ __device__ Record update_phase(const IterArgs &a, int i, float4 *cen, double4 *c
             }
         }
     }
+    gather_totals<NT, PACKED>(T, a.k, tot);
+    __syncthreads();
     int flags = 0;
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
         const int c = tid + r * NT;
         if (c < a.k) {
+            if (update) cv[r] = totals_to_center<PACKED>(tot, c, cv[r]);
             cen[c] = make_float4((float)cv[r].x, (float)cv[r].y, (float)cv[r].z, 0.0f);
             if (cen64) cen64[c] = cv[r];
             flags |= center_flags(cv[r]);
@@ -271,10 +297,12 @@ __device__ void finish_block(const IterArgs &a, int i, int vb, int mode, const f
         });
     }
     __syncthreads();
-    unsigned long long *T = a.sv.totals + (size_t)(i % 3) * kMaxK * 4;
+    // this block's copy of the totals slot (see kTotCopies)
+    unsigned long long *T =
+        a.sv.totals + (size_t)(i % 3) * kTotSlot + (blockIdx.x % kTotCopies) * kTotCopy;
     for (int c = tid; c < a.k * NACC; c += NT) {
         const unsigned long long v = acc[c];
-        if (v != 0ull) atomicAdd(&T[(c / NACC) * 4 + (c % NACC)], v);
+        if (v != 0ull) atomicAdd(&T[c], v);
     }
     unsigned long long e = ev;
     block_sum2<NT>(sse, e, dscr, uscr);
@@ -402,6 +430,7 @@ __device__ void search_chunk(const IterArgs &a, int i, int vb, int mode, const f
 // several of them (the batched form) can overlay them.
 struct RowsLds {
     float4 cen[kMaxK];
+    unsigned long long tot[kMaxK * 4];
     __align__(16) unsigned long long keys[kMaxK];
     uint32_t rank[kMaxK];
     double dscr[kSortThreads / 64];
@@ -426,6 +455,7 @@ struct SearchLds {
 template <int NT>
 struct FinalLds {
     float4 cen[kMaxK];
+    unsigned long long tot[kMaxK * 4];
     double4 cen64[kMaxK];
     double dscr[NT / 64];
     unsigned long long uscr[NT / 64];
@@ -438,11 +468,10 @@ struct FinalLds {
 template <bool PACKED>
 __device__ void rows_body(const IterArgs &a, int i, int p0, int p1, RowsLds &L) {
     const Record rec =
-        update_phase<kSortThreads, PACKED>(a, i, L.cen, nullptr, p0 == 0, L.dscr, L.uscr);
+        update_phase<kSortThreads, PACKED>(a, i, L.cen, nullptr, p0 == 0, L.dscr, L.uscr, L.tot);
     if (rec.converged) return;
     if (p0 == 0) {
-        unsigned long long *T = a.sv.totals + (size_t)(i % 3) * kMaxK * 4;
-        for (int c = threadIdx.x; c < kMaxK * 4; c += kSortThreads) T[c] = 0ull;
+        clear_totals<kSortThreads, PACKED>(a.sv.totals + (size_t)(i % 3) * kTotSlot, a.k);
     }
     for (int p = p0; p < p1; ++p)
         sort_row<kSortThreads>(L.cen, a.k, p, L.keys, L.rank, a.sv.rows + (size_t)p * kRowStride,
@@ -508,10 +537,9 @@ __device__ void search_body(const IterArgs &a, int i, int vb, SearchLds<DEFER> &
 // slot step i accumulates into is cleared.  Returns the record.
 template <int NT, bool PACKED>
 __device__ Record update_body(const IterArgs &a, int i, FinalLds<NT> &L) {
-    const Record r = update_phase<NT, PACKED>(a, i, L.cen, L.cen64, true, L.dscr, L.uscr);
+    const Record r = update_phase<NT, PACKED>(a, i, L.cen, L.cen64, true, L.dscr, L.uscr, L.tot);
     if (!r.converged) {
-        unsigned long long *T = a.sv.totals + (size_t)(i % 3) * kMaxK * 4;
-        for (int c = threadIdx.x; c < kMaxK * 4; c += NT) T[c] = 0ull;
+        clear_totals<NT, PACKED>(a.sv.totals + (size_t)(i % 3) * kTotSlot, a.k);
     }
     __syncthreads();
     __threadfence();
@@ -534,14 +562,14 @@ __device__ void sort_body(const IterArgs &a, int i, int p0, int p1, RowsLds &L) 
 template <int NT, bool PACKED>
 __device__ void final_body(const IterArgs &a, int i, FinalLds<NT> &L) {
     const int tid = threadIdx.x;
-    const Record r = update_phase<NT, PACKED>(a, i, L.cen, L.cen64, true, L.dscr, L.uscr);
+    const Record r = update_phase<NT, PACKED>(a, i, L.cen, L.cen64, true, L.dscr, L.uscr, L.tot);
     __syncthreads();
     for (int c = tid; c < a.k; c += NT) {
         a.sv.pal[c] = L.cen[c];
         a.sv.pal64[c] = L.cen64[c];
     }
     unsigned long long *T0 = a.sv.totals;
-    for (int c = tid; c < kMaxK * 4; c += NT) T0[c] = 0ull;
+    for (int c = tid; c < (int)kTotSlot; c += NT) T0[c] = 0ull;
     if (tid == 0) {
         a.sv.hdr->rec[0] = r;
         a.sv.hdr->info[0] = r.iters;

@@ -82,11 +82,10 @@ __global__ __launch_bounds__(kSearchThreads) void fused_step_kernel(IterArgs a, 
     uint32_t key[kCpt], cnt[kCpt];
     int pm[kCpt];
     prefetch_points(a, blockIdx.x, key, cnt, pm);
-    const Record rec = update_phase<NT, PACKED>(a, i, cen, cen64, blockIdx.x == 0, dscr, uscr);
+    const Record rec = update_phase<NT, PACKED>(a, i, cen, cen64, blockIdx.x == 0, dscr, uscr, acc);
     if (rec.converged) return;
     if (blockIdx.x == 0) {
-        unsigned long long *Tn = a.sv.totals + (size_t)((i + 1) % 3) * kMaxK * 4;
-        for (int c = tid; c < kMaxK * 4; c += NT) Tn[c] = 0ull;
+        clear_totals<NT, PACKED>(a.sv.totals + (size_t)((i + 1) % 3) * kTotSlot, a.k);
     }
     for (int c = tid; c < K * NACC; c += NT) acc[c] = 0ull;
     const int p = tid / kFusedMaxK, t = tid % kFusedMaxK;
@@ -129,11 +128,10 @@ __global__ __launch_bounds__(kSearchThreads) void full_step_kernel(IterArgs a, i
     uint32_t key[kCpt], cnt[kCpt];
     int pm[kCpt];
     prefetch_points(a, blockIdx.x, key, cnt, pm);
-    const Record rec = update_phase<NT, PACKED>(a, i, cen, cen64, blockIdx.x == 0, dscr, uscr);
+    const Record rec = update_phase<NT, PACKED>(a, i, cen, cen64, blockIdx.x == 0, dscr, uscr, acc);
     if (rec.converged) return;
     if (blockIdx.x == 0) {
-        unsigned long long *Tn = a.sv.totals + (size_t)((i + 1) % 3) * kMaxK * 4;
-        for (int c = tid; c < kMaxK * 4; c += NT) Tn[c] = 0ull;
+        clear_totals<NT, PACKED>(a.sv.totals + (size_t)((i + 1) % 3) * kTotSlot, a.k);
     }
     for (int c = tid; c < a.k * NACC; c += NT) acc[c] = 0ull;
     __syncthreads();
@@ -191,7 +189,7 @@ __global__ void init_state_kernel(StateView sv, int k, int points, int grid,
         sv.pal[c] = v;
         sv.pal64[c] = make_double4((double)v.x, (double)v.y, (double)v.z, 0.0);
     }
-    for (int64_t c = gt; c < 3 * kMaxK * 4; c += stride) sv.totals[c] = 0ull;
+    for (int64_t c = gt; c < 3 * (int64_t)kTotSlot; c += stride) sv.totals[c] = 0ull;
     for (int64_t c = gt; c < 2 * kMaxGrid; c += stride) {
         sv.sse_part[c] = 0.0;
         sv.eval_part[c] = 0ull;

@@ -73,8 +73,16 @@ static_assert(offsetof(Header, info) == 128, "header layout");
 constexpr size_t kOffHeader = 0;
 constexpr size_t kOffPalette = 256;                                   // float4[2][256]
 constexpr size_t kOffPal64 = kOffPalette + 2 * kMaxK * 16;            // double4[2][256]
-constexpr size_t kOffTotals = kOffPal64 + 2 * kMaxK * 32;             // u64[3][256][4]
-constexpr size_t kOffSsePart = kOffTotals + 3 * kMaxK * 4 * 8;        // double[2][kMaxGrid]
+// Center totals: three slots (filled, read, cleared by step parity mod 3),
+// each with kTotCopies copies of u64[256][4].  A block adds into the copy of
+// its physical index mod kTotCopies; workgroups are dealt to the 8 XCDs in
+// turn, so each copy takes the atomics of one XCD and no line moves between
+// the XCDs' L2 caches.  Readers add the copies (exact integers).
+constexpr int kTotCopies = 8;
+constexpr size_t kTotCopy = (size_t)kMaxK * 4;                        // u64 words per copy
+constexpr size_t kTotSlot = kTotCopies * kTotCopy;                     // u64 words per slot
+constexpr size_t kOffTotals = kOffPal64 + 2 * kMaxK * 32;             // u64[3][kTotCopies][256][4]
+constexpr size_t kOffSsePart = kOffTotals + 3 * kTotSlot * 8;         // double[2][kMaxGrid]
 constexpr size_t kOffEvalPart = kOffSsePart + 2 * kMaxGrid * 8;       // u64[2][kMaxGrid]
 constexpr size_t kOffSseHist = kOffEvalPart + 2 * kMaxGrid * 8;       // double[kHistory]
 constexpr size_t kOffEvalHist = kOffSseHist + kHistory * 8;           // int64[kHistory]

@@ -44,7 +44,7 @@ def _tables(wsm, seed0=0):
     return out
 
 
-@pytest.mark.parametrize("split", ["default", "coarse"])
+@pytest.mark.parametrize("split", ["problem", "tuned", "coarse"])
 def test_batch_equals_single_image_iterate(split):
     wsm = _wsm()
     _say("batch of", len(CASES), "uneven images, work split", split)
@@ -56,12 +56,15 @@ def test_batch_equals_single_image_iterate(split):
         r.iterate(mi, eps)
         ref.append(r)
         states.append(wsm.init(col, cnt, n_pix, pal))
-    if split == "default":
+    if split in ("problem", "tuned"):
+        # each problem's own grid (the single-image launch's), or the
+        # autotuned split from the committed table
         grid, rpi = None, None
     else:  # few large search blocks, many rows per rows item
         grid = [max(1, st.n_points // 16384) for st in states]
         rpi = [16] * len(states)
-    b = wsm.Batch(states, [c[2] for c in CASES], [c[3] for c in CASES], grid, rpi)
+    b = wsm.Batch(states, [c[2] for c in CASES], [c[3] for c in CASES], grid, rpi,
+                  tuned=(split == "tuned"))
     try:
         for rep in range(2):
             if rep:
@@ -77,7 +80,7 @@ def test_batch_equals_single_image_iterate(split):
                 s1, e1 = st.history()
                 s2, e2 = r.history()
                 assert np.array_equal(e1, e2), (rep, j)
-                if split == "default":
+                if split == "problem":
                     assert np.array_equal(s1, s2), (rep, j)
                 else:  # another number of search blocks: the SSE sums in another order
                     np.testing.assert_allclose(s1, s2, rtol=SUM_RTOL)
