@@ -79,8 +79,9 @@ __host__ __device__ constexpr uint32_t make_item(uint32_t image, uint32_t kind, 
 }
 
 union BatchLds {
-    SearchLds<true> d;
-    SearchLds<false> n;
+    SearchLds<kVarDefer> d;
+    SearchLds<kVarLane> l;
+    SearchLds<kVarFirst> n;
     RowsLds r;
     FinalLds<kSearchThreads> f;
 };
@@ -193,11 +194,11 @@ __global__ __launch_bounds__(kSearchThreads) void batch_kernel(const BatchImage 
             const int p1 = p0 + B.rows_per_item < a.k ? p0 + B.rows_per_item : a.k;
             sort_body(a, step, p0, p1, L.r);
         } else if (step == 0) {
-            search_body<true, false, true>(a, step, (int)idx, L.n);
+            search_body<true, kVarFirst>(a, step, (int)idx, L.n);
         } else if (a.k >= kDeferMinK) {
-            search_body<true, true, false>(a, step, (int)idx, L.d);
+            search_body<true, kVarDefer>(a, step, (int)idx, L.d);
         } else {
-            search_body<true, false, false>(a, step, (int)idx, L.n);
+            search_body<true, kVarLane>(a, step, (int)idx, L.l);
         }
         // completion of the item; the last one of the phase goes on
         __syncthreads();

@@ -5,6 +5,8 @@
 // step structure is described in iterate.hip.
 #pragma once
 
+#include <type_traits>
+
 #include "sm_block.h"
 
 namespace wsm {
@@ -320,13 +322,13 @@ __device__ void finish_block(const IterArgs &a, int i, int vb, int mode, const f
 // cen64), and the SSE is summed from float64 distances.  Adds the block's
 // sums into totals slot i % 3 and writes its SSE and evaluation partials.
 
-template <bool PACKED, bool FULL, bool DEFER>
+template <bool PACKED, bool FULL, bool DEFER, bool TAB = false>
 __device__ void search_chunk(const IterArgs &a, int i, int vb, int mode, const float4 *cen,
                              const double4 *cen64, const uint8_t *Ms, unsigned long long *acc,
                              double *dscr, unsigned long long *uscr, DeferQueue *dq,
                              uint32_t (&key)[kCpt], uint32_t (&cnt)[kCpt], int (&pm)[kCpt],
                              bool first = false, const float *Dd = nullptr,
-                             FlatScratch *fs = nullptr) {
+                             FlatScratch *fs = nullptr, const float4 *Tb = nullptr, int ts = 0) {
     constexpr int NT = kSearchThreads;
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x;
@@ -381,6 +383,10 @@ __device__ void search_chunk(const IterArgs &a, int i, int vb, int mode, const f
                         best = full_scan<true>(x, y, z, pr, a.k, cen, bd, s2, fev);
                     ev += FULL ? fev : sm_scan_evals(x, y, z, pr, a.k, cen, Ms, rs);
                 }
+            } else if (TAB) {
+                if (valid)
+                    best = sm_scan_tab(x, y, z, pr, a.k, cen, Ms, rs, Tb, ts, bd, prev, s2, dj,
+                                       ev);
             } else if (!DEFER) {
                 if (valid) best = sm_scan(x, y, z, pr, a.k, cen, Ms, rs, bd, prev, s2, dj, ev);
             } else {
@@ -437,20 +443,31 @@ struct RowsLds {
     unsigned long long uscr[kSortThreads / 64];
 };
 
-template <bool DEFER>
+template <int V>
 struct SearchLds {
+    static constexpr bool kDefer = V == kVarDefer;
     float4 cen[kMaxK];
     double4 cen64[kMaxK];
     unsigned long long acc[kMaxK * 4];
     // rows of M: the first kRowPrefix entries when scans defer, else whole
-    __align__(16) uint8_t Ms[kMaxK * (DEFER ? kRowPrefix : kRowStride)];
-    // with DEFER: the distances of those entries, and the flat scans' scratch
-    __align__(16) float Dd[DEFER ? kMaxK * kRowDist : 4];
-    FlatScratch fs[DEFER ? kSearchThreads / 64 : 1];
-    DeferQueue dq;
+    __align__(16) uint8_t Ms[var_ms_bytes<V>()];
+    // kVarTable: the row tables (sm_scan_tab)
+    float4 Tb[V == kVarTable ? kTableMaxK * kTableStride : 1];
+    // kVarDefer: the distances of the row heads, and the flat scans' scratch
+    __align__(16) float Dd[kDefer ? kMaxK * kRowDist : 4];
+    FlatScratch fs[kDefer ? kSearchThreads / 64 : 1];
+    typename std::conditional<kDefer, DeferQueue, NoQueue>::type dq;
     double dscr[kSearchThreads / 64];
     unsigned long long uscr[kSearchThreads / 64];
 };
+
+template <int V>
+__device__ __forceinline__ DeferQueue *queue_of(SearchLds<V> &L) {
+    if constexpr (V == kVarDefer)
+        return &L.dq;
+    else
+        return nullptr;
+}
 
 template <int NT>
 struct FinalLds {
@@ -480,10 +497,11 @@ __device__ void rows_body(const IterArgs &a, int i, int p0, int p1, RowsLds &L) 
 
 // Sort-means step i, search part (kSearchThreads threads), block vb of
 // a.grid: the centers and M copied into LDS, then the block's points.
-template <bool PACKED, bool DEFER, bool FIRST>
-__device__ void search_body(const IterArgs &a, int i, int vb, SearchLds<DEFER> &L) {
+template <bool PACKED, int V>
+__device__ void search_body(const IterArgs &a, int i, int vb, SearchLds<V> &L) {
     constexpr int NT = kSearchThreads;
     constexpr int NACC = PACKED ? 2 : 4;
+    constexpr bool DEFER = V == kVarDefer, FIRST = V == kVarFirst, TAB = V == kVarTable;
     const int tid = threadIdx.x;
     uint32_t key[kCpt], cnt[kCpt];
     int pm[kCpt];
@@ -522,13 +540,29 @@ __device__ void search_body(const IterArgs &a, int i, int vb, SearchLds<DEFER> &
         }
     }
     for (int c = tid; c < a.k * NACC; c += NT) L.acc[c] = 0ull;
-    if (tid == 0) L.dq.n = 0u;
+    if constexpr (DEFER) {
+        if (tid == 0) L.dq.n = 0u;
+    }
     __syncthreads();
+    if constexpr (TAB) {
+        // row tables from the rows and centers now in LDS: wave w builds rows
+        // w, w + NW, ..., lane j entry j
+        const int n = a.k - 1, rs = lds_row_stride(a.k), lane = tid & 63;
+        for (int p = tid >> 6; p < a.k; p += NT / 64) {
+            if (lane < n) {
+                const float4 cp = L.cen[p], ct = L.cen[L.Ms[p * rs + lane]];
+                L.Tb[p * kTableStride + lane] =
+                    make_float4(ct.x, ct.y, ct.z, sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z));
+            }
+        }
+        __syncthreads();
+    }
     // The launch for a call's first step (FIRST) checks whether the state has
     // completed no step yet, i.e. every membership is still 0 (state init).
     const bool first = FIRST && rec.iters == 0;
-    search_chunk<PACKED, false, DEFER>(a, i, vb, rec.mode, L.cen, L.cen64, L.Ms, L.acc, L.dscr,
-                                       L.uscr, &L.dq, key, cnt, pm, first, L.Dd, L.fs);
+    search_chunk<PACKED, false, DEFER, TAB>(a, i, vb, rec.mode, L.cen, L.cen64, L.Ms, L.acc,
+                                            L.dscr, L.uscr, queue_of(L), key, cnt, pm, first,
+                                            L.Dd, L.fs, L.Tb, kTableStride);
 }
 
 

@@ -45,10 +45,10 @@ __global__ __launch_bounds__(kSortThreads) void rows_kernel(IterArgs a, int i) {
 
 // Sort-means step i, second launch: every block copies the centers and M
 // into LDS and searches its chunk.
-template <bool PACKED, bool DEFER, bool FIRST>
+template <bool PACKED, int V>
 __global__ __launch_bounds__(kSearchThreads) void search_kernel(IterArgs a, int i) {
-    __shared__ SearchLds<DEFER> L;
-    search_body<PACKED, DEFER, FIRST>(a, i, blockIdx.x, L);
+    __shared__ SearchLds<V> L;
+    search_body<PACKED, V>(a, i, blockIdx.x, L);
 }
 
 // Rows of M for palette slot 0 of the state (the pixel map's palette).
@@ -63,8 +63,9 @@ __global__ __launch_bounds__(kSortThreads) void palette_rows_kernel(StateView sv
 
 // Sort-means step for K <= kFusedMaxK in one launch: every block applies
 // the update as in the rows launch, sorts all K rows of M into LDS itself
-// (thread (p, t) ranks center t in row p) and searches its points.  Totals
-// slots follow the comparator's order: clear (i + 1) % 3, add into i % 3.
+// (thread (p, t) ranks center t in row p, and also writes the row table
+// entry) and searches its points.  Totals slots follow the comparator's
+// order: clear (i + 1) % 3, add into i % 3.
 template <bool PACKED>
 __global__ __launch_bounds__(kSearchThreads) void fused_step_kernel(IterArgs a, int i) {
     __shared__ float4 cen[kMaxK];
@@ -72,6 +73,7 @@ __global__ __launch_bounds__(kSearchThreads) void fused_step_kernel(IterArgs a, 
     __shared__ unsigned long long acc[kMaxK * 4];
     __shared__ __align__(16) unsigned long long keys[kFusedMaxK * kFusedMaxK];
     __shared__ __align__(16) uint8_t Ms[kFusedMaxK * kFusedMaxK];
+    __shared__ float4 Tb[kFusedMaxK * kFusedMaxK];
     __shared__ double dscr[kSearchThreads / 64];
     __shared__ unsigned long long uscr[kSearchThreads / 64];
     constexpr int NT = kSearchThreads;
@@ -91,8 +93,10 @@ __global__ __launch_bounds__(kSearchThreads) void fused_step_kernel(IterArgs a, 
     const int p = tid / kFusedMaxK, t = tid % kFusedMaxK;
     const bool entry = p < K && t < K && t != p;
     unsigned long long kt = ~0ull;
+    float4 ct = make_float4(0.f, 0.f, 0.f, 0.f);
     if (entry) {
-        const float4 cp = cen[p], ct = cen[t];
+        const float4 cp = cen[p];
+        ct = cen[t];
         kt = ((unsigned long long)__float_as_uint(sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z))
               << 32) | (unsigned)t;
     }
@@ -107,10 +111,14 @@ __global__ __launch_bounds__(kSearchThreads) void fused_step_kernel(IterArgs a, 
             r += (uint32_t)(v.x < kt) + (uint32_t)(v.y < kt);
         }
         Ms[p * lds_row_stride(K) + r] = (uint8_t)t;
+        Tb[p * kFusedMaxK + r] = make_float4(ct.x, ct.y, ct.z, __uint_as_float((uint32_t)(kt >> 32)));
     }
     __syncthreads();
-    search_chunk<PACKED, false, false>(a, i, blockIdx.x, rec.mode, cen, cen64, Ms, acc, dscr, uscr,
-                                       nullptr, key, cnt, pm);
+    // a fresh state (no step completed) starts from center 0 everywhere:
+    // the full scan gives the same centers (see search_chunk)
+    search_chunk<PACKED, false, false, true>(a, i, blockIdx.x, rec.mode, cen, cen64, Ms, acc, dscr,
+                                             uscr, nullptr, key, cnt, pm, rec.iters == 0, nullptr,
+                                             nullptr, Tb, kFusedMaxK);
 }
 
 // Full-search comparator: one launch per step, the update applied
@@ -354,9 +362,12 @@ static int launch_steps(const IterArgs &a, int max_iters, bool full, hipStream_t
         } else {
             WSM_LAUNCH(WSM_KERNEL_ROWS, rows_kernel<PACKED>, dim3(a.k), dim3(kSortThreads), stream,
                        a, i);
-            const auto search = i == 0 ? search_kernel<PACKED, false, true>
-                                : a.k >= kDeferMinK ? search_kernel<PACKED, true, false>
-                                                    : search_kernel<PACKED, false, false>;
+            const bool table =
+                a.k <= kTableMaxK && a.pts.n >= (int64_t)a.grid * kTableMinPoints;
+            const auto search = i == 0              ? search_kernel<PACKED, kVarFirst>
+                                : a.k >= kDeferMinK ? search_kernel<PACKED, kVarDefer>
+                                : table             ? search_kernel<PACKED, kVarTable>
+                                                    : search_kernel<PACKED, kVarLane>;
             WSM_LAUNCH(WSM_KERNEL_SEARCH, search, dim3(a.grid), dim3(kSearchThreads), stream, a,
                        i);
         }

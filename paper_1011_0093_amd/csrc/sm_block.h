@@ -37,6 +37,10 @@ constexpr int kDeferCap = 1024;                  // deferred scans per block
 constexpr int kDeferBatch = 8;                   // deferred scans a wave fetches rows for at once
 constexpr int kDeferMinK = 128;                  // smallest K whose search defers
 constexpr int kFusedMaxK = 32;                   // largest K sorted inside the search block
+constexpr int kTableMaxK = 64;                   // largest K whose search keeps row tables
+constexpr int kTableMinPoints = 2048;            // points per search block that pay for them
+constexpr int kTableStride = 64;                 // entries per row of a row table
+static_assert(kTableMaxK - 1 <= kTableStride, "a table row holds the whole row of M");
 
 // LDS row stride for K centers: K - 1 entries rounded up to 16 bytes.
 __host__ __device__ constexpr int lds_row_stride(int K) { return ((K - 1) + 15) / 16 * 16; }
@@ -273,6 +277,67 @@ __device__ __forceinline__ int sm_scan(float x, float y, float z, int p, int K,
                 if (j + e >= n || dpt[e] >= thr) {
                     stop = true;
                     if (j + e < n) dj = dpt[e];
+                } else {
+                    ev += 1;
+                    s2 = fminf(s2, fmaxf(d[e], bd));
+                    if (better_center(d[e], bd, t[e], best, p)) {
+                        bd = d[e];
+                        best = t[e];
+                    }
+                }
+            }
+        }
+        if (stop) break;
+    }
+    best_d = bd;
+    prev_out = prev;
+    s2_out = s2;
+    dj_out = dj;
+    return best;
+}
+
+// sm_scan over a row table: entry j of row p is also kept as the float4
+// (c_t, d(c_p, c_t)^2) in Tb[p * ts + j] (t = the row's entry j), so a batch
+// of kScanBatch entries takes one round of LDS reads -- the row's 8 indices
+// and the 8 table entries, whose addresses are all known -- instead of the
+// center reads waiting for the indices.  The stored d(c_p, c_t)^2 is the
+// value the rows were sorted by.  Same results as sm_scan.  Reads past the
+// row's K - 1 entries stay inside the row and its table row (ts and rs are
+// at least K - 1 rounded up to kScanBatch); their values are not used.
+__device__ __forceinline__ int sm_scan_tab(float x, float y, float z, int p, int K,
+                                           const float4 *cen, const uint8_t *Ms, int rs,
+                                           const float4 *Tb, int ts, float &best_d,
+                                           float &prev_out, float &s2_out, float &dj_out,
+                                           uint32_t &ev) {
+    const float4 cp = cen[p];
+    const float prev = sq_dist(x, y, z, cp.x, cp.y, cp.z);
+    const float thr = prev * kBreakScale;
+    float bd = prev;
+    float s2 = kNoSkip, dj = kNoSkip;
+    int best = p;
+    ev += 1;
+    const uint8_t *row = Ms + p * rs;
+    const float4 *tr = Tb + p * ts;
+    const int n = K - 1;
+    for (int j = 0; j < n; j += kScanBatch) {
+        const uint2 w8 = *(const uint2 *)(row + j);
+        float4 ce[kScanBatch];
+#pragma unroll
+        for (int e = 0; e < kScanBatch; ++e) ce[e] = tr[j + e];
+        float d[kScanBatch];
+        int t[kScanBatch];
+#pragma unroll
+        for (int e = 0; e < kScanBatch; ++e) {
+            t[e] = ((e < 4 ? w8.x : w8.y) >> (8 * (e & 3))) & 0xFFu;
+            d[e] = sq_dist(x, y, z, ce[e].x, ce[e].y, ce[e].z);
+        }
+        bool stop = false;
+#pragma unroll
+        for (int e = 0; e < kScanBatch; ++e) {
+            if (!stop) {
+                if (j + e >= n || ce[e].w >= thr) {
+                    stop = true;
+                    if (j + e < n) dj = ce[e].w;
                 } else {
                     ev += 1;
                     s2 = fminf(s2, fmaxf(d[e], bd));
@@ -557,6 +622,28 @@ struct DeferQueue {
     uint32_t s2[kDeferCap];     // second smallest distance so far (float bits)
     uint32_t pjb[kDeferCap];    // next entry << 16 | previous center << 8 | best center
 };
+struct NoQueue {};
+
+// How a search launch holds M in LDS and scans it:
+//   kVarFirst: whole rows (a call's first step: the full scan on a fresh
+//              state, else sm_scan);
+//   kVarLane:  whole rows, sm_scan;
+//   kVarTable: K <= kTableMaxK, whole rows and their row tables, sm_scan_tab
+//              (built by every block: used where a block has at least
+//              kTableMinPoints points);
+//   kVarDefer: K >= kDeferMinK, the row heads and their distances, flat
+//              scans (sm_scan_flat), longer scans deferred.
+constexpr int kVarFirst = 0;
+constexpr int kVarLane = 1;
+constexpr int kVarTable = 2;
+constexpr int kVarDefer = 3;
+// LDS bytes of M for a variant
+template <int V>
+constexpr int var_ms_bytes() {
+    return V == kVarDefer ? kMaxK * kRowPrefix
+                          : V == kVarTable ? kTableMaxK * lds_row_stride(kTableMaxK)
+                                           : kMaxK * kRowStride;
+}
 
 // Finishes a block's deferred scans (Ms holds row heads of kRowPrefix
 // entries, rows the whole rows in device memory), in three phases:
