@@ -31,7 +31,7 @@ constexpr int kRowStride = kMaxK;                // bytes per row of M in device
 constexpr int kScanBatch = 8;                    // row entries fetched per scan step
 static_assert(kScanBatch == 8, "a scan batch is one 8-byte word of a row, read aligned");
 static_assert(kMaxK % kScanBatch == 0, "a batched full scan stays inside the center table");
-constexpr int kRowPrefix = 32;                   // row head scanned flat (in LDS when scans defer)
+constexpr int kRowPrefix = 64;                   // row head scanned flat (in LDS when scans defer)
 static_assert(kRowPrefix == kRowDist, "the stored distances cover the LDS row prefix");
 constexpr int kDeferCap = 1024;                  // deferred scans per block
 constexpr int kDeferBatch = 8;                   // deferred scans a wave fetches rows for at once
@@ -439,7 +439,8 @@ struct FlatScratch {
                                  // offset of its pair q's row entry: p * kRowPrefix - first pair
     unsigned long long bk[64];   // lane l: smallest scan_key so far
     uint32_t near[64];           // lane l: a near tie with its best was seen
-    __align__(16) uint8_t head[64 * kRowPrefix];  // pair q: 1 + the lane whose pairs start at q
+    uint8_t head[64];            // pair q0 + k of the current round: 1 + the lane whose
+                                 // pairs start there, else 0
 };
 
 // Sort-means scans of a wave's points (lane l: the point with color `key` and
@@ -450,9 +451,11 @@ struct FlatScratch {
 //   Row p is ascending in d(c_p, c_t)^2, so the entries before the break are
 // the first n, n = the number of stored distances Dd[p][.] below the
 // threshold (a binary search).  The wave lists its (point, entry) pairs in
-// lane order; lane l takes pairs l, l + 64, ..., finds the pair's point from
-// the marks of where each point's pairs start (a running maximum over the
-// wave), and folds the pair's scan_key into that point's LDS minimum (a
+// lane order and takes them in rounds of 64, lane l pair q0 + l of round q0;
+// it finds the pair's point from the marks of where each point's pairs start
+// (the lanes whose first pair falls in the round write them; a running
+// maximum over the wave spreads them), and folds the pair's scan_key into
+// that point's LDS minimum (a
 // row never lists its own center, so the pair's key is that of a center
 // other than the previous one).
 //   The result is the sequential scan's: bd, best, evaluations 1 + n, and
@@ -491,16 +494,10 @@ __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, in
     const uint32_t incl = wave_incl_sum((uint32_t)n);
     const int excl = (int)incl - n;
     const int total = (int)wave_last_u32(incl);
-    uint4 *h4 = (uint4 *)fs.head;
-    static_assert(sizeof(fs.head) == 64 * 2 * 16, "two 16-byte stores per lane clear the marks");
-    h4[lane] = make_uint4(0u, 0u, 0u, 0u);
-    h4[lane + 64] = make_uint4(0u, 0u, 0u, 0u);
+    fs.head[lane] = 0u;
     fs.pt[lane] = make_float4(x, y, z, __int_as_float(pp * kRowPrefix - excl));
     fs.bk[lane] = scan_key(prev, pp, pp);
     fs.near[lane] = 0u;
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    if (n > 0) fs.head[excl] = (uint8_t)(lane + 1);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     uint32_t carry = 0u;
     // A pair's key is compared with the minimum it met one iteration late,
     // so the wait for the returned value overlaps the next iteration's LDS
@@ -510,7 +507,16 @@ __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, in
     for (int q0 = 0; q0 < total; q0 += 64) {  // wave-uniform
         const int q = q0 + lane;
         const bool act = q < total;
-        const uint32_t hq = act ? (uint32_t)fs.head[q] : 0u;
+        // this round's marks: written, read, and cleared again by their
+        // writers (a wave's LDS operations take effect in issue order)
+        const bool mark = n > 0 && excl >= q0 && excl < q0 + 64;
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (mark) fs.head[excl - q0] = (uint8_t)(lane + 1);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const uint32_t hq = act ? (uint32_t)fs.head[lane] : 0u;
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (mark) fs.head[excl - q0] = 0u;
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (pend_o >= 0 && near_pair(key_dist(pend_kq), key_dist(pend_old))) fs.near[pend_o] = 1u;
         pend_o = -1;
         uint32_t o1 = wave_incl_max(hq);

@@ -88,7 +88,7 @@ constexpr size_t kOffSseHist = kOffEvalPart + 2 * kMaxGrid * 8;       // double[
 constexpr size_t kOffEvalHist = kOffSseHist + kHistory * 8;           // int64[kHistory]
 constexpr size_t kOffMapPart = kOffEvalHist + kHistory * 8;           // double[kMaxGrid]
 constexpr size_t kOffRows = align_up(kOffMapPart + kMaxGrid * 8, 256);  // u8[256][256]
-constexpr int kRowDist = 32;  // leading entries of each row whose distances are kept
+constexpr int kRowDist = 64;  // leading entries of each row whose distances are kept
 constexpr size_t kOffRowDist = kOffRows + (size_t)kMaxK * kMaxK;  // float[256][kRowDist]
 constexpr size_t kOffMembership = kOffRowDist + (size_t)kMaxK * kRowDist * 4;
 
