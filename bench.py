@@ -47,17 +47,17 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/search_kernel_512x512_traffic.md).  It describes the kernel
 # sources it was measured on (hash below); for any other sources the bench
 # reports null.
-SEARCH_TRAFFIC_BYTES = 3540284
-SEARCH_TRAFFIC_SRC = "ed9ca8dacc69ed8e"
-_KERNEL_SOURCES = ("iterate.hip", "sm_block.h", "wave_ops.h", "wsm_internal.h")
+SEARCH_TRAFFIC_BYTES = 3832379
+SEARCH_TRAFFIC_SRC = "af140073651656ec"
+_KERNEL_SOURCES = ("iterate.hip", "iter_device.h", "sm_block.h", "wave_ops.h", "wsm_internal.h")
 
 # The same for the 4096x4096 reduction (partition + compaction, bytes per
 # call) and pixel gather (bytes per launch)
 # (profiles/reduce_map_4096x4096_traffic.md).
-REDUCE_TRAFFIC_BYTES = 188613911
-REDUCE_TRAFFIC_SRC = "7a85f2a8e6e8d236"
-GATHER_TRAFFIC_BYTES = 106184633
-GATHER_TRAFFIC_SRC = "7b9861d30065b11f"
+REDUCE_TRAFFIC_BYTES = 188630155
+REDUCE_TRAFFIC_SRC = "53436acf8cb2f32b"
+GATHER_TRAFFIC_BYTES = 106378505
+GATHER_TRAFFIC_SRC = "25426c20ea0a05ee"
 _REDUCE_SOURCES = ("reduce.hip", "wave_ops.h", "wsm_internal.h")
 _MAP_SOURCES = ("map.hip", "sm_block.h", "wave_ops.h", "wsm_internal.h")
 
@@ -332,11 +332,12 @@ def main():
             mse_wsm=float(out[K][1].item()), mse_full=float(mse_full.item()))
 
     # ---- roofline of the dominant kernel: the sort-means search launch at
-    # K = 256 from the second step on (search_kernel<true, true, false>; the
-    # first step of a call runs its own variant, K = 64 the variant without
-    # deferred scans and K <= 32 one fused launch per step), timed per launch
-    # with events the runtime records at the kernel.  Algorithmic bytes per
-    # color and iteration: 4 (key) + 4 (count) + 1 (membership read) + 1 (write).
+    # K = 256 from the second step on (search_kernel<true, 3>: row heads in
+    # LDS, flattened scans, long scans deferred; the first step of a call runs
+    # its own variant, K = 64 the lane-scan variant and K <= 32 one fused
+    # launch per step), timed per launch with events the runtime records at
+    # the kernel.  Algorithmic bytes per color and iteration: 4 (key) +
+    # 4 (count) + 1 (membership read) + 1 (write).
     launches = []
     for K in Ks:
         if K < 128:
@@ -353,7 +354,7 @@ def main():
     traffic = None
     if SEARCH_TRAFFIC_BYTES is not None and kernel_sources_hash() == SEARCH_TRAFFIC_SRC:
         traffic = SEARCH_TRAFFIC_BYTES
-    roofline = dict(kernel="wsm::search_kernel<true, true, false>", bound="hbm", achieved=achieved,
+    roofline = dict(kernel="wsm::search_kernel<true, 3>", bound="hbm", achieved=achieved,
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                     traffic_unit="bytes per launch", avg_launch_us=dur_ms * 1e3,
                     launches=len(launches), bytes_per_launch=bytes_per_launch)
