@@ -492,7 +492,8 @@ __device__ void rows_body(const IterArgs &a, int i, int p0, int p1, RowsLds &L) 
     }
     for (int p = p0; p < p1; ++p)
         sort_row<kSortThreads>(L.cen, a.k, p, L.keys, L.rank, a.sv.rows + (size_t)p * kRowStride,
-                               a.sv.rowd + (size_t)p * kRowDist);
+                               a.sv.rowd + (size_t)p * kRowDist,
+                               a.k <= kTableMaxK ? a.sv.rowt + (size_t)p * kTableStride : nullptr);
 }
 
 // Sort-means step i, search part (kSearchThreads threads), block vb of
@@ -525,11 +526,29 @@ __device__ void search_body(const IterArgs &a, int i, int vb, SearchLds<V> &L) {
                                                : make_uint4(0u, 0u, 0u, 0u);
         }
     }
+    // kVarTable: the row tables the rows launch wrote
+    constexpr int kTbRegs = TAB ? kTableMaxK * kTableStride / NT : 1;
+    static_assert(!TAB || kTableMaxK * kTableStride == kTbRegs * NT, "table copy");
+    float4 treg[kTbRegs];
+    if (TAB) {
+#pragma unroll
+        for (int u = 0; u < kTbRegs; ++u) {
+            const int q = tid + u * NT;
+            treg[u] = q < a.k * kTableStride ? a.sv.rowt[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
     const Record rec = a.sv.hdr->rec[(i + 1) & 1];
     if (rec.converged) return;
     if (tid < a.k) {
         L.cen[tid] = pc;
         L.cen64[tid] = pc64;
+    }
+    if (TAB) {
+#pragma unroll
+        for (int u = 0; u < kTbRegs; ++u) {
+            const int q = tid + u * NT;
+            if (q < a.k * kTableStride) L.Tb[q] = treg[u];
+        }
     }
     store_rows<NT, DEFER>(R, a.k, L.Ms);
     if (DEFER) {
@@ -544,19 +563,7 @@ __device__ void search_body(const IterArgs &a, int i, int vb, SearchLds<V> &L) {
         if (tid == 0) L.dq.n = 0u;
     }
     __syncthreads();
-    if constexpr (TAB) {
-        // row tables from the rows and centers now in LDS: wave w builds rows
-        // w, w + NW, ..., lane j entry j
-        const int n = a.k - 1, rs = lds_row_stride(a.k), lane = tid & 63;
-        for (int p = tid >> 6; p < a.k; p += NT / 64) {
-            if (lane < n) {
-                const float4 cp = L.cen[p], ct = L.cen[L.Ms[p * rs + lane]];
-                L.Tb[p * kTableStride + lane] =
-                    make_float4(ct.x, ct.y, ct.z, sq_dist(cp.x, cp.y, cp.z, ct.x, ct.y, ct.z));
-            }
-        }
-        __syncthreads();
-    }
+
     // The launch for a call's first step (FIRST) checks whether the state has
     // completed no step yet, i.e. every membership is still 0 (state init).
     const bool first = FIRST && rec.iters == 0;

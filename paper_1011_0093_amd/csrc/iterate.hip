@@ -362,12 +362,10 @@ static int launch_steps(const IterArgs &a, int max_iters, bool full, hipStream_t
         } else {
             WSM_LAUNCH(WSM_KERNEL_ROWS, rows_kernel<PACKED>, dim3(a.k), dim3(kSortThreads), stream,
                        a, i);
-            const bool table =
-                a.k <= kTableMaxK && a.pts.n >= (int64_t)a.grid * kTableMinPoints;
-            const auto search = i == 0              ? search_kernel<PACKED, kVarFirst>
-                                : a.k >= kDeferMinK ? search_kernel<PACKED, kVarDefer>
-                                : table             ? search_kernel<PACKED, kVarTable>
-                                                    : search_kernel<PACKED, kVarLane>;
+            const auto search = i == 0                ? search_kernel<PACKED, kVarFirst>
+                                : a.k >= kDeferMinK   ? search_kernel<PACKED, kVarDefer>
+                                : a.k <= kTableMaxK   ? search_kernel<PACKED, kVarTable>
+                                                      : search_kernel<PACKED, kVarLane>;
             WSM_LAUNCH(WSM_KERNEL_SEARCH, search, dim3(a.grid), dim3(kSearchThreads), stream, a,
                        i);
         }

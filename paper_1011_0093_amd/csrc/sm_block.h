@@ -37,9 +37,8 @@ constexpr int kDeferCap = 1024;                  // deferred scans per block
 constexpr int kDeferBatch = 8;                   // deferred scans a wave fetches rows for at once
 constexpr int kDeferMinK = 128;                  // smallest K whose search defers
 constexpr int kFusedMaxK = 32;                   // largest K sorted inside the search block
-constexpr int kTableMaxK = 64;                   // largest K whose search keeps row tables
-constexpr int kTableMinPoints = 2048;            // points per search block that pay for them
-constexpr int kTableStride = 64;                 // entries per row of a row table
+constexpr int kTableMaxK = kRowTabRows;          // largest K whose search keeps row tables
+constexpr int kTableStride = kRowTabStride;      // entries per row of a row table
 static_assert(kTableMaxK - 1 <= kTableStride, "a table row holds the whole row of M");
 
 // LDS row stride for K centers: K - 1 entries rounded up to 16 bytes.
@@ -66,11 +65,13 @@ __device__ __forceinline__ bool run_tail(int key, bool valid) {
 // their bit patterns order like the values, and the keys are distinct.  The
 // rank of each key is counted by NT / kMaxK threads over slices of the
 // others.  If drow is not null, the distances of the first kRowDist entries
-// are written to it as well.  All NT threads call it; it starts with a
-// barrier, so consecutive calls may reuse the scratch.
+// are written to it as well, and if trow is not null the row table (entry j
+// as (c_t, d(c_p, c_t)^2), for K <= kRowTabRows).  All NT threads call it;
+// it starts with a barrier, so consecutive calls may reuse the scratch.
 template <int NT>
 __device__ void sort_row(const float4 *cen, int K, int p, unsigned long long *__restrict__ keys,
-                         uint32_t *rank, uint8_t *__restrict__ row, float *__restrict__ drow) {
+                         uint32_t *rank, uint8_t *__restrict__ row, float *__restrict__ drow,
+                         float4 *__restrict__ trow = nullptr) {
     static_assert(NT % kMaxK == 0, "block size");
     constexpr int Q = NT / kMaxK;
     constexpr int span = kMaxK / Q;
@@ -113,7 +114,12 @@ __device__ void sort_row(const float4 *cen, int K, int p, unsigned long long *__
         if (c != p) {
             const uint32_t rk = rank[c];
             row[rk] = (uint8_t)c;
-            if (drow && rk < (uint32_t)kRowDist) drow[rk] = __uint_as_float((uint32_t)(keys[c] >> 32));
+            const float d = __uint_as_float((uint32_t)(keys[c] >> 32));
+            if (drow && rk < (uint32_t)kRowDist) drow[rk] = d;
+            if (trow) {
+                const float4 ct = cen[c];
+                trow[rk] = make_float4(ct.x, ct.y, ct.z, d);
+            }
         }
     }
 }
@@ -634,9 +640,7 @@ struct NoQueue {};
 //   kVarFirst: whole rows (a call's first step: the full scan on a fresh
 //              state, else sm_scan);
 //   kVarLane:  whole rows, sm_scan;
-//   kVarTable: K <= kTableMaxK, whole rows and their row tables, sm_scan_tab
-//              (built by every block: used where a block has at least
-//              kTableMinPoints points);
+//   kVarTable: K <= kTableMaxK, whole rows and their row tables, sm_scan_tab;
 //   kVarDefer: K >= kDeferMinK, the row heads and their distances, flat
 //              scans (sm_scan_flat), longer scans deferred.
 constexpr int kVarFirst = 0;
