@@ -80,10 +80,11 @@ def test_batch_equals_single_image_iterate(split):
                 s1, e1 = st.history()
                 s2, e2 = r.history()
                 assert np.array_equal(e1, e2), (rep, j)
-                if split == "problem":
-                    assert np.array_equal(s1, s2), (rep, j)
-                else:  # another number of search blocks: the SSE sums in another order
-                    np.testing.assert_allclose(s1, s2, rtol=SUM_RTOL)
+                # float64 SSE sums: the batched form's search blocks (and, for
+                # other splits, their number) add the terms in another order
+                # than the single-image launches, whose deferred scans add
+                # theirs in queue order
+                np.testing.assert_allclose(s1, s2, rtol=SUM_RTOL)
     finally:
         b.close()
 
