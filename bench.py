@@ -668,6 +668,15 @@ def bench_differentiable(torch, wsm, synth, B=16, size=512, K=64):
 
     t_ours = _timed(torch, ours, reps=10)
     t_plain = _timed(torch, plain, reps=10)
+    # the library's two calls alone (D, then both gradients) on preallocated
+    # buffers: the kernels' share of the autograd step
+    d_buf = torch.empty(B, dtype=torch.float64, device=x.device)
+    g_buf = torch.ones(B, dtype=torch.float64, device=x.device)
+    gx_buf = torch.empty_like(xf)
+    gc_buf = torch.empty_like(pal)
+    ws = wsm.distortion_workspace(B, xf.shape[1], K, x.device)
+    t_kern = _timed(torch, lambda: wsm.distortion_into(xf, pal, idx, d_buf, ws, g_buf, gx_buf,
+                                                       gc_buf), reps=20)
     gx, gc = ours()
     px, pc = plain()
     n_pix = size * size
@@ -676,6 +685,8 @@ def bench_differentiable(torch, wsm, synth, B=16, size=512, K=64):
                 speedup_vs_torch=t_plain / t_ours,
                 bytes_fwd_bwd=float(B * n_pix * (13 + 13 + 12)),
                 achieved_gbs=B * n_pix * (13 + 13 + 12) / (t_ours * 1e-3) / 1e9,
+                kernels_fwd_bwd_ms=t_kern,
+                kernels_achieved_gbs=B * n_pix * (13 + 13 + 12) / (t_kern * 1e-3) / 1e9,
                 max_rel_diff_grad_x=float(((gx - px).abs().max() / px.abs().max()).item()),
                 max_rel_diff_grad_palette=float(((gc - pc).abs().max() / pc.abs().max()).item()),
                 images_per_s_forward_backward=B / ((t_fwd + t_ours) * 1e-3))

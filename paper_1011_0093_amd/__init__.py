@@ -22,7 +22,8 @@ import torch  # imported before the library so both share one HIP runtime
 __all__ = [
     "WsmError", "library_path", "reduce_colors", "reduce_colors_into",
     "State", "IterateGraph", "init", "init_pixels", "map_pixels", "palette_from_indices",
-    "quantize", "distortion", "quantize_batch", "Batch", "MAX_K", "HISTORY",
+    "quantize", "distortion", "distortion_into", "distortion_workspace", "quantize_batch",
+    "Batch", "MAX_K", "HISTORY",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -548,6 +549,30 @@ class _Distortion(torch.autograd.Function):
         return gx, gc, None
 
 
+def distortion_into(x: torch.Tensor, palette: torch.Tensor, index: torch.Tensor,
+                    d: torch.Tensor, workspace: torch.Tensor, grad_d: torch.Tensor = None,
+                    grad_x: torch.Tensor = None, grad_palette: torch.Tensor = None) -> None:
+    """The differentiable form's two calls on caller-owned buffers, without
+    autograd: D into d (float64 [B]); and, when grad_d (float64 [B]) is
+    given, the adjoint into grad_x and/or grad_palette.  Shapes as for
+    distortion() ([B, N, 3] colors, [B, K, 3] palettes, [B, N] indices);
+    workspace: uint8, at least wsm_distortion_workspace_bytes."""
+    B, N, _ = x.shape
+    K = palette.shape[1]
+    _check(_lib.wsm_distortion(_ptr(x), _ptr(index), _ptr(palette), B, N, K, _ptr(d),
+                               _ptr(workspace), workspace.numel(), _stream()), "wsm_distortion")
+    if grad_d is not None:
+        _check(_lib.wsm_distortion_backward(
+            _ptr(x), _ptr(index), _ptr(palette), B, N, K, _ptr(grad_d),
+            _ptr(grad_x), _ptr(grad_palette),
+            _ptr(workspace), workspace.numel(), _stream()), "wsm_distortion_backward")
+
+
+def distortion_workspace(batch: int, n: int, k: int, device) -> torch.Tensor:
+    """A workspace for distortion_into (uint8 device tensor)."""
+    return _distortion_workspace(batch, n, k, device)
+
+
 def distortion(x: torch.Tensor, palette: torch.Tensor, index: torch.Tensor) -> torch.Tensor:
     """Per-image distortion D_i = (1/N) sum_p ||x_ip - c_{i,index(p)}||^2
     (float64 [B]) with the assignment frozen, differentiable in x (float32
@@ -564,19 +589,45 @@ def distortion(x: torch.Tensor, palette: torch.Tensor, index: torch.Tensor) -> t
 def quantize_batch(x: torch.Tensor, k: int, init_indices_fn, max_iters: int = 50,
                    eps: float = 1e-4):
     """Forward pass of the differentiable form for a batch of float32 images
-    (B, H, W, 3) whose values are 8-bit colors: WSM on each image (reduce,
-    init from ``init_indices_fn(n_unique, k)``, iterate, map).  Returns
-    (palette float32 [B, k, 3], index uint8 [B, H*W], states)."""
+    (B, H, W, 3) whose values are 8-bit colors: WSM on each image -- every
+    image reduced (one read-back of the B unique-color counts), its state
+    initialised from ``init_indices_fn(n_unique, k)``, all of them iterated
+    by one launch of the batched form (each image's result is that of
+    State.iterate), then mapped.  Returns (palette float32 [B, k, 3], index
+    uint8 [B, H*W], states)."""
     x = _dev(x, torch.float32, "x")
     B = x.shape[0]
     u8 = x.round().clamp(0, 255).to(torch.uint8)
     if not torch.equal(u8.to(torch.float32), x):
         raise WsmError("quantize_batch: x must hold 8-bit color values")
-    pals, idxs, states = [], [], []
+    u8 = u8.reshape(B, -1).contiguous()
+    n = u8.shape[1] // 3
+    dev = u8.device
+    cap = min(n, 1 << 24)
+    colors = torch.empty((B, cap), dtype=torch.int32, device=dev)
+    counts = torch.empty((B, cap), dtype=torch.int32, device=dev)
+    nu = torch.empty(B, dtype=torch.int32, device=dev)
+    ws = torch.empty(reduce_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    for b in range(B):  # in stream order, so they share the workspace
+        reduce_colors_into(u8[b], colors[b], counts[b], nu[b:b + 1], ws)
+    nus = nu.cpu().tolist()
+    if min(nus) < 1:
+        raise WsmError("device error in wsm_reduce_colors")
+    states = []
     for b in range(B):
-        img = u8[b].contiguous()
-        st, idx, _, _ = quantize(img, k, init_indices_fn, max_iters, eps, want_rgb=False)
-        pals.append(st.palette())
-        idxs.append(idx)
-        states.append(st)
-    return torch.stack(pals).contiguous(), torch.stack(idxs).contiguous(), states
+        c, w = colors[b, :nus[b]], counts[b, :nus[b]]
+        states.append(init(c, w, n, palette_from_indices(c, init_indices_fn(nus[b], k))))
+    for b0 in range(0, B, 128):  # at most 128 images per batched launch
+        batch = Batch(states[b0:b0 + 128], max_iters, eps)
+        try:
+            batch.launch()
+            if batch.error() != 0:
+                raise WsmError("batched iterations reported a device error")
+        finally:
+            batch.close()
+    lut = torch.empty(1 << 24, dtype=torch.uint8, device=dev)
+    idx = torch.empty((B, n), dtype=torch.uint8, device=dev)
+    for b in range(B):  # the table is rewritten at every image's keys before it is read
+        map_pixels_into(states[b], u8[b], lut, idx[b])
+    pals = torch.stack([st.palette() for st in states]).contiguous()
+    return pals, idx, states

@@ -129,17 +129,42 @@ __global__ __launch_bounds__(kAdjThreads) void distortion_grad_kernel(
     }
 }
 
-// dD/dc of image i: for each (center, channel), the block sums added in
-// block order, times -2 g / n.
+// dD/dc of image i: for each (center, channel) e, the block sums added in a
+// fixed order -- wave w of kRedWaves sums blocks w, w + kRedWaves, ... in
+// order (lane l: element e0 + l), then the waves' sums are added in wave
+// order -- times -2 g / n.  The loads of kRedBatch blocks are issued
+// together.
+constexpr int kRedWaves = kAdjThreads / 64;
+constexpr int kRedBatch = 8;
+
 __global__ __launch_bounds__(kAdjThreads) void grad_palette_reduce_kernel(
     const double *__restrict__ part, int64_t tiles, int64_t n, int k,
     const double *__restrict__ grad_d, float *__restrict__ grad_pal) {
+    __shared__ double ws[kRedWaves][64];
     const int64_t img = blockIdx.y;
-    const int e = blockIdx.x * kAdjThreads + threadIdx.x;  // center * 3 + channel
-    if (e >= k * 3) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;  // center * 3 + channel
+    const bool in = e < k * 3;
+    const double *pi = part + img * tiles * k * 3 + e;
     double s = 0.0;
-    for (int64_t b = 0; b < tiles; ++b) s += part[(img * tiles + b) * k * 3 + e];
-    grad_pal[img * k * 3 + e] = (float)(-2.0 * grad_d[img] / (double)n * s);
+    for (int64_t b0 = wave; b0 < tiles; b0 += (int64_t)kRedWaves * kRedBatch) {
+        double v[kRedBatch];
+#pragma unroll
+        for (int u = 0; u < kRedBatch; ++u) {
+            const int64_t b = b0 + (int64_t)u * kRedWaves;
+            v[u] = in && b < tiles ? pi[b * k * 3] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kRedBatch; ++u) s += v[u];
+    }
+    ws[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && in) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kRedWaves; ++w) t += ws[w][lane];
+        grad_pal[img * k * 3 + e] = (float)(-2.0 * grad_d[img] / (double)n * t);
+    }
 }
 
 }  // namespace wsm
@@ -199,8 +224,7 @@ extern "C" int wsm_distortion_backward(const float *x, const uint8_t *index, con
                              stream>>>(x, index, palette, n_pixels, k, L.tiles, grad_d, grad_x,
                                        part);
     if (grad_palette)
-        grad_palette_reduce_kernel<<<dim3((unsigned)((k * 3 + kAdjThreads - 1) / kAdjThreads),
-                                          (unsigned)batch),
+        grad_palette_reduce_kernel<<<dim3((unsigned)((k * 3 + 63) / 64), (unsigned)batch),
                                      dim3(kAdjThreads), 0, stream>>>(part, L.tiles, n_pixels, k,
                                                                      grad_d, grad_palette);
     return hipGetLastError() == hipSuccess ? WSM_OK : WSM_EHIP;
