@@ -623,8 +623,16 @@ def bench_batched(torch, wsm, synth, n_images=64):
     bat_mse = [float(b["mse"].item()) for b in bufs]
     same = all(torch.equal(a.palette64().cpu(), seq_states[j].palette64().cpu())
                for j, a in enumerate(holder["states"]))
-    # the persistent launch alone
-    t_launch = _timed(torch, lambda: (prepare(), plan.launch()), reps=2) - _timed(torch, prepare, reps=2)
+    # the persistent launch alone, and the same iterations as 64 back-to-back
+    # iterate calls (no host synchronisation between them)
+    t_prep = _timed(torch, prepare, reps=2)
+    t_launch = _timed(torch, lambda: (prepare(), plan.launch()), reps=2) - t_prep
+
+    def iterate_calls():
+        for st in prepare():
+            st.iterate(MAX_ITERS, EPS)
+
+    t_calls = _timed(torch, iterate_calls, reps=2) - t_prep
     plan.close()
     n_pix = sum(g.numel() // 3 for g in imgs)
     return dict(workload=f"{n_images} images, side U[128,1024] (seeded), K from {{16,32,64,128,256}}, "
@@ -632,7 +640,8 @@ def bench_batched(torch, wsm, synth, n_images=64):
                 n_images=n_images, n_pixels=n_pix, sequential_ms=t_seq, batched_ms=t_bat,
                 images_per_s_sequential=n_images / (t_seq * 1e-3),
                 images_per_s_batched=n_images / (t_bat * 1e-3), speedup=t_seq / t_bat,
-                persistent_launch_ms_est=t_launch, plan_create_ms=t_plan,
+                persistent_launch_ms_est=t_launch, iterate_calls_ms_est=t_calls,
+                speedup_launch_vs_iterate_calls=t_calls / t_launch, plan_create_ms=t_plan,
                 images_per_s_batched_with_plan=n_images / ((t_bat + t_plan) * 1e-3),
                 equal_palettes=bool(same),
                 max_rel_mse_diff=max(abs(a - b) / b for a, b in zip(bat_mse, seq_mse)),

@@ -128,9 +128,14 @@ __device__ void enqueue(BatchCtl *ctl, uint32_t *items, uint32_t *ready, uint32_
     }
     for (uint32_t j = threadIdx.x; j < n_new; j += blockDim.x)
         items[base + j] = make_item(image, kind, j);
-    __threadfence();
-    for (uint32_t j = threadIdx.x; j < n_new; j += blockDim.x)
-        __hip_atomic_store(&ready[base + j], run, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    // one release fence (the first wave's), after which that wave publishes
+    // the ready words: the block's item stores come before it
+    if (threadIdx.x < 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        for (uint32_t j = threadIdx.x; j < n_new; j += 64)
+            __hip_atomic_store(&ready[base + j], run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 __global__ __launch_bounds__(kSearchThreads) void batch_kernel(const BatchImage *__restrict__ img,
@@ -148,13 +153,16 @@ __global__ __launch_bounds__(kSearchThreads) void batch_kernel(const BatchImage 
             uint32_t item = kNoItem;
             const uint32_t slot = atomicAdd(&ctl->head, 1u);
             const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+            // relaxed polls; one acquire fence once the slot is ready (an
+            // acquire at every poll would invalidate the L2 each time)
             for (;;) {
-                if (slot < cap && __hip_atomic_load(&ready[slot], __ATOMIC_ACQUIRE,
+                if (slot < cap && __hip_atomic_load(&ready[slot], __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT) == run) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     item = items[slot];
                     break;
                 }
-                if (__hip_atomic_load(&ctl->remaining, __ATOMIC_ACQUIRE,
+                if (__hip_atomic_load(&ctl->remaining, __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT) <= 0)
                     break;
                 if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {
@@ -204,14 +212,16 @@ __global__ __launch_bounds__(kSearchThreads) void batch_kernel(const BatchImage 
         __syncthreads();
         if (tid == 0) {
             const uint32_t total = kind == kItemRows ? (uint32_t)B.rows_items : (uint32_t)a.grid;  // start items return above
-            __threadfence();
+            // release the block's results, count the item; the last one
+            // acquires everyone else's
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const uint32_t old = atomicAdd(&ictl[im].done, 1u);
-            __threadfence();
             s_last = (old + 1u == total) ? 1 : 0;
             if (s_last) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 // ready for the next phase's items, which are published later
+                // (after the release fence in enqueue)
                 __hip_atomic_store(&ictl[im].done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __threadfence();
             }
         }
         __syncthreads();
