@@ -115,6 +115,8 @@ def parse():
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-k-sweep", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--single-stream", action="store_true",
+                    help="run the three K of a step one after another on one stream")
     ap.add_argument("--no-oracle-timings", action="store_true")
     ap.add_argument("--no-differentiable", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -159,8 +161,13 @@ def main():
     # one state buffer per K, re-initialised every step (persistent buffers,
     # as a serving loop would keep them)
     states = {}
+    # the three K of a step are independent: by default each runs (init,
+    # iterate, map) on a HIP stream of its own (default priority), after the
+    # shared reduction, so that their latency-bound launches overlap
+    k_streams = {K: torch.cuda.Stream(device=dev) for K in Ks}
+    luts = {K: torch.empty(1 << 24, dtype=torch.uint8, device=dev) for K in Ks}
 
-    def step(record=None):
+    def step(single_stream=args.single_stream):
         wsm.reduce_colors_into(img, colors, counts, nu, ws)
         n_unique = int(nu.item())  # the caller needs N' to draw the initial subset
         col, cnt = colors[:n_unique], counts[:n_unique]
@@ -170,16 +177,24 @@ def main():
                 synth.init_indices(args.seed, n_unique, K).astype(np.int32))
             off += K
         idx_dev.copy_(idx_host, non_blocking=True)
+        ready = torch.cuda.Event()
+        ready.record(stream)
         off = 0
         out = {}
         for K in Ks:
-            pal = wsm.palette_from_indices(col, idx_dev[off:off + K])
+            s_k = stream if single_stream else k_streams[K]
+            s_k.wait_event(ready)
+            with torch.cuda.stream(s_k):
+                pal = wsm.palette_from_indices(col, idx_dev[off:off + K])
+                st = wsm.init(col, cnt, N, pal, reuse=states.get(K))
+                states[K] = st
+                st.iterate(MAX_ITERS, EPS)
+                index, _, mse = wsm.map_pixels(st, img, lut=lut if single_stream else luts[K])
             off += K
-            st = wsm.init(col, cnt, N, pal, reuse=states.get(K))
-            states[K] = st
-            st.iterate(MAX_ITERS, EPS)
-            index, _, mse = wsm.map_pixels(st, img, lut=lut)
             out[K] = (st, mse, pal)
+        if not single_stream:
+            for K in Ks:
+                stream.wait_stream(k_streams[K])
         return n_unique, out
 
     if args.copy_mb > 0:
@@ -208,6 +223,20 @@ def main():
     wall = time.perf_counter() - t0
     ms_step = e0.elapsed_time(e1) / args.steps
     ms_step_wall = wall * 1000.0 / args.steps
+    # the same step with the three K one after another on one stream
+    ms_single = None
+    if not args.single_stream:
+        for _ in range(args.warmup):
+            step(single_stream=True)
+        torch.cuda.synchronize()
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        for _ in range(args.steps):
+            step(single_stream=True)
+        s1.record(stream)
+        torch.cuda.synchronize()
+        ms_single = s0.elapsed_time(s1) / args.steps
 
     # ---- the same step with each K's iterate launches replayed from a
     # caller-owned HIP graph, recorded once outside the timed region (the
@@ -227,13 +256,21 @@ def main():
                     synth.init_indices(args.seed, n_u, K).astype(np.int32))
                 o += K
             idx_dev.copy_(idx_host, non_blocking=True)
+            ready_g = torch.cuda.Event()
+            ready_g.record(stream)
             o = 0
             for K in Ks:
-                pal_g = wsm.palette_from_indices(col_g, idx_dev[o:o + K])
+                s_k = stream if args.single_stream else k_streams[K]
+                s_k.wait_event(ready_g)
+                with torch.cuda.stream(s_k):
+                    pal_g = wsm.palette_from_indices(col_g, idx_dev[o:o + K])
+                    st_g = wsm.init(col_g, cnt_g, N, pal_g, reuse=states[K])
+                    graphs[K].launch()
+                    wsm.map_pixels(st_g, img, lut=lut if args.single_stream else luts[K])
                 o += K
-                st_g = wsm.init(col_g, cnt_g, N, pal_g, reuse=states[K])
-                graphs[K].launch()
-                wsm.map_pixels(st_g, img, lut=lut)
+            if not args.single_stream:
+                for K in Ks:
+                    stream.wait_stream(k_streams[K])
 
         for _ in range(args.warmup):
             step_graph()
@@ -252,7 +289,8 @@ def main():
         graph_leg = dict(ms_per_step=ms_graph, images_per_s=len(Ks) / (ms_graph * 1e-3),
                          equal_to_direct=bool(same),
                          note="iterate launches of each K replayed from a caller-owned HIP graph "
-                              "(wsm_iterate_graph_*); reduce, init and map launched directly")
+                              "(wsm_iterate_graph_*), on the K's stream; reduce, init and map "
+                              "launched directly")
 
     per_k = {}
     color_iters = 0
@@ -270,6 +308,10 @@ def main():
     value = color_iters / (ms_step * 1e-3)
     if graph_leg is not None:
         graph_leg["value"] = color_iters / (graph_leg["ms_per_step"] * 1e-3)
+    single_leg = None
+    if ms_single is not None:
+        single_leg = dict(ms_per_step=ms_single, images_per_s=len(Ks) / (ms_single * 1e-3),
+                          value=color_iters / (ms_single * 1e-3))
 
     # ---- per-phase times and the full-search comparators (separate passes)
     def timed(fn, reps=5):
@@ -401,7 +443,10 @@ def main():
         "ms_per_step_wall": ms_step_wall,
         "ms_per_step_p10_p50_p90": [float(np.percentile(step_ms, q)) for q in (10, 50, 90)],
         "images_per_s": len(Ks) / (ms_step * 1e-3),
-        "launches": "direct (no graph replay)",
+        "launches": ("direct (no graph replay), one stream" if args.single_stream else
+                     "direct (no graph replay); after the shared reduction each K on a HIP stream "
+                     "of its own"),
+        "single_stream": single_leg,
         "graph_replay": graph_leg,
         "higher_is_better": True,
         "scaling": "weak",
