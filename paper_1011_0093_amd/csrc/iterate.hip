@@ -12,13 +12,15 @@
 //      (Sec. 2: the inter-center distances with every row sorted).
 // Step i, search launch (one block per chunk of points):
 //   3. sort-means from each point's previous center over an LDS copy of M
-//      (for K >= kDeferMinK a wave's scans over the row heads are spread
-//      over its lanes, and the rare longer ones finished by whole waves);
+//      (the launch variants kVar* of sm_block.h: for K <= kTableMaxK with
+//      the row tables, for K >= kDeferMinK a wave's scans over the row
+//      heads spread over its lanes and the rare longer ones finished by
+//      whole waves);
 //   4. sums count * (R, G, B, 1) per center: runs of equal centers within a
 //      wave are pre-summed with a segmented scan, then added into LDS, and
-//      each block flushes its non-zero sums with 64-bit device atomics (the
-//      second level of the reduction); the block's SSE and evaluation count
-//      go to per-block partials.
+//      each block flushes its non-zero sums with 64-bit device atomics into
+//      its XCD's copy of the totals (the second level of the reduction);
+//      the block's SSE and evaluation count go to per-block partials.
 // The full-search comparator does 1, 3 (full search) and 4 in one launch.
 // The sums are exact integers, so the result does not depend on the order
 // of the additions and the pruned search, the full search and k-means on the

@@ -6,18 +6,20 @@
 // left out, since the scan starts from the second one.  It is built once per
 // set of centers (sort_row, one block per row) and kept in device memory as
 // K rows of kRowStride bytes, with the distances of each row's first
-// kRowDist entries; a search block copies the rows (for K >= kDeferMinK only
-// their first kRowPrefix entries and those distances) into LDS.  (For K <=
-// kFusedMaxK every search block sorts the rows itself.)  A scan compares
-// d(c_p, c_t)^2 recomputed from the centers in LDS, or the stored value,
-// with the same expression the rows were sorted by, so the break test sees
-// bit-equal values.
+// kRowDist entries and, for K <= kTableMaxK, row tables (entry j of row p as
+// (c_t, d(c_p, c_t)^2)); a search block copies the rows (for K >= kDeferMinK
+// only their first kRowPrefix entries and those distances, for K <=
+// kTableMaxK with the tables) into LDS.  (For K <= kFusedMaxK every search
+// block sorts the rows itself.)  A scan compares d(c_p, c_t)^2 recomputed
+// from the centers in LDS, or the stored value, with the same expression the
+// rows were sorted by, so the break test sees bit-equal values.
 //
 // For K < kDeferMinK a lane scans its own point's row, kScanBatch entries
-// at a time (sm_scan).  For K >= kDeferMinK a wave scans the row heads of
-// its 64 points together, with the entries dealt out evenly over the lanes
-// (sm_scan_flat), and the rare scans that go past the head are finished by
-// the whole wave (sm_finish_wave), so that no lane holds its wave.
+// at a time (sm_scan, or sm_scan_tab over the row tables).  For K >=
+// kDeferMinK a wave scans the row heads of its 64 points together, with the
+// entries dealt out evenly over the lanes (sm_scan_flat), and the rare scans
+// that go past the head are finished by the whole wave (sm_finish_wave), so
+// that no lane holds its wave.
 #pragma once
 
 #include "wave_ops.h"
