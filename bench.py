@@ -166,6 +166,10 @@ def main():
     # shared reduction, so that their latency-bound launches overlap
     k_streams = {K: torch.cuda.Stream(device=dev) for K in Ks}
     luts = {K: torch.empty(1 << 24, dtype=torch.uint8, device=dev) for K in Ks}
+    # search blocks of each K while the three share the GPU (of 256 CUs): the
+    # longest chain (K = 256) keeps three quarters, K = 64 half, K = 16 a
+    # quarter (chosen by measurement; results do not depend on the grid)
+    share_grid = {16: 64, 64: 128, 256: 192}
 
     def step(single_stream=args.single_stream):
         wsm.reduce_colors_into(img, colors, counts, nu, ws)
@@ -188,6 +192,8 @@ def main():
                 pal = wsm.palette_from_indices(col, idx_dev[off:off + K])
                 st = wsm.init(col, cnt, N, pal, reuse=states.get(K))
                 states[K] = st
+                if not single_stream and K in share_grid:
+                    st.grid = min(st.grid, share_grid[K])
                 st.iterate(MAX_ITERS, EPS)
                 index, _, mse = wsm.map_pixels(st, img, lut=lut if single_stream else luts[K])
             off += K
@@ -243,6 +249,9 @@ def main():
     # same image every step, so the recorded arguments stay valid)
     graph_leg = None
     if not args.no_graph:
+        if not args.single_stream:
+            for K in Ks:
+                states[K].grid = min(states[K].grid, share_grid[K])
         graphs = {K: states[K].graph(MAX_ITERS, EPS) for K in Ks}
         ref64 = {K: states[K].palette64().cpu() for K in Ks}
 

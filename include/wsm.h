@@ -106,7 +106,14 @@ typedef struct wsm_problem {
     const uint32_t *counts;
     const uint8_t *rgb;     /* PIXELS: the image the state is bound to */
     uint32_t magic;         /* set by wsm_init / wsm_init_pixels */
-    int32_t grid;           /* search-kernel blocks, chosen at init */
+    int32_t grid;           /* search-kernel blocks, chosen at init (one per
+                               compute unit, fewer for small tables); the
+                               caller may set any value in 1..2048 before an
+                               iterate call, e.g. fewer blocks so that work on
+                               other streams gets compute units: memberships,
+                               centers, evaluation counts and stopping do not
+                               depend on it, the float64 SSE sums only in the
+                               order of their terms */
 } wsm_problem;
 
 /* Host-only: bytes of state for n_points points and k centers. */

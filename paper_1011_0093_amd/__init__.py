@@ -226,6 +226,20 @@ class State:
     def n_pixels(self) -> int:
         return int(self.prob.n_pixels)
 
+    @property
+    def grid(self) -> int:
+        """Blocks of the search launch (wsm_problem.grid)."""
+        return int(self.prob.grid)
+
+    @grid.setter
+    def grid(self, blocks: int) -> None:
+        """Fewer (or more) search blocks for the following iterate calls,
+        1..2048, e.g. to share the GPU with work on other streams; the
+        results do not depend on it (the SSE's last bits aside)."""
+        if not 1 <= int(blocks) <= 2048:
+            raise WsmError("grid must be in 1..2048")
+        self.prob.grid = int(blocks)
+
     def iterate(self, max_iters: int = 50, eps: float = 1e-4) -> None:
         """Sort-means iterations (asynchronous on the current stream)."""
         _check(_lib.wsm_iterate(ctypes.byref(self.prob), int(max_iters), float(eps), _stream()),

@@ -422,6 +422,36 @@ def test_resume_equals_single_call(K):
 
 
 @pytest.mark.parametrize("K", [16, 64, 256])
+def test_caller_grid_gives_the_same_results(K):
+    """A caller-chosen search grid (wsm_problem.grid: fewer blocks, as when
+    several K share the GPU on streams of their own, or more) gives the
+    default grid's memberships, centers, evaluation counts and record; the
+    SSE history within SUM_RTOL (its terms added in another order)."""
+    wsm = _wsm()
+    img = synth.workload_image("medium", 0)
+    _say("caller grid medium seed 0 K", K)
+    g = _gpu_img(img)
+    col, cnt = wsm.reduce_colors(g)
+    n_pix = img.shape[0] * img.shape[1]
+    pal = wsm.palette_from_indices(col, synth.init_indices(0, col.numel(), K))
+    ref = wsm.init(col, cnt, n_pix, pal)
+    ref.iterate(12, 1e-4)
+    for grid in (1, 37, 96, 700):
+        st = wsm.init(col, cnt, n_pix, pal)
+        st.grid = grid
+        st.iterate(12, 1e-4)
+        assert np.array_equal(st.membership().cpu().numpy(), ref.membership().cpu().numpy()), grid
+        assert np.array_equal(st.palette64().cpu().numpy(), ref.palette64().cpu().numpy()), grid
+        assert st.info() == ref.info(), grid
+        assert np.array_equal(st.history()[1], ref.history()[1]), grid
+        np.testing.assert_allclose(st.history()[0], ref.history()[0], rtol=SUM_RTOL)
+    with pytest.raises(wsm.WsmError):
+        st.grid = 0
+    with pytest.raises(wsm.WsmError):
+        st.grid = 2049
+
+
+@pytest.mark.parametrize("K", [16, 64, 256])
 def test_unpacked_sums_equal_packed(K):
     # Counts x 300 push 255 * n_pixels past 2^32, so the centroid sums take
     # four u64 per center instead of two packed ones.  Scaling every weight
