@@ -183,20 +183,20 @@ def main():
         idx_dev.copy_(idx_host, non_blocking=True)
         ready = torch.cuda.Event()
         ready.record(stream)
-        off = 0
+        offs = dict(zip(Ks, np.cumsum([0] + Ks[:-1]).tolist()))
         out = {}
-        for K in Ks:
+        # concurrent: the longest chain (largest K) is enqueued first
+        for K in (Ks if single_stream else sorted(Ks, reverse=True)):
             s_k = stream if single_stream else k_streams[K]
             s_k.wait_event(ready)
             with torch.cuda.stream(s_k):
-                pal = wsm.palette_from_indices(col, idx_dev[off:off + K])
+                pal = wsm.palette_from_indices(col, idx_dev[offs[K]:offs[K] + K])
                 st = wsm.init(col, cnt, N, pal, reuse=states.get(K))
                 states[K] = st
                 if not single_stream and K in share_grid:
                     st.grid = min(st.grid, share_grid[K])
                 st.iterate(MAX_ITERS, EPS)
                 index, _, mse = wsm.map_pixels(st, img, lut=lut if single_stream else luts[K])
-            off += K
             out[K] = (st, mse, pal)
         if not single_stream:
             for K in Ks:
@@ -267,16 +267,15 @@ def main():
             idx_dev.copy_(idx_host, non_blocking=True)
             ready_g = torch.cuda.Event()
             ready_g.record(stream)
-            o = 0
-            for K in Ks:
+            offs_g = dict(zip(Ks, np.cumsum([0] + Ks[:-1]).tolist()))
+            for K in (Ks if args.single_stream else sorted(Ks, reverse=True)):
                 s_k = stream if args.single_stream else k_streams[K]
                 s_k.wait_event(ready_g)
                 with torch.cuda.stream(s_k):
-                    pal_g = wsm.palette_from_indices(col_g, idx_dev[o:o + K])
+                    pal_g = wsm.palette_from_indices(col_g, idx_dev[offs_g[K]:offs_g[K] + K])
                     st_g = wsm.init(col_g, cnt_g, N, pal_g, reuse=states[K])
                     graphs[K].launch()
                     wsm.map_pixels(st_g, img, lut=lut if args.single_stream else luts[K])
-                o += K
             if not args.single_stream:
                 for K in Ks:
                     stream.wait_stream(k_streams[K])
