@@ -10,10 +10,13 @@
 //              grouped by slice (a tile-local counting sort), 2 bytes per
 //              pixel with 16-byte stores, together with an (offset, count)
 //              word per (slice, tile).
-//   compact    one block per slice.  The slice's (offset, count) words are
-//              loaded first; then sixteen lanes read one tile's segment of
-//              the slice together with 16-byte loads, several segments'
-//              loads in flight at once, into a 2^15-bin LDS histogram; the
+//   compact    one block per slice.  Each wave takes the slice's segments
+//              in a set of tiles (one (offset, count) word per lane), lays
+//              them end to end as a list of 16-byte pieces and deals the
+//              pieces out to its lanes, 64 per round and kRoundsInFlight
+//              rounds' loads in flight at once, so that nearly every lane
+//              counts 8 of the slice's keys per round into a 2^15-bin LDS
+//              histogram however long or short the segments are; the
 //              non-empty bins are compacted in
 //              ascending order, and the slice's place in the output comes
 //              from a decoupled look-back over the slices before it, 64
@@ -31,8 +34,8 @@ constexpr int kPartThreads = 1024;
 constexpr int kMaxPpt = 16;                       // pixels per thread (max)
 constexpr int kMaxTile = kPartThreads * kMaxPpt;  // 16384 pixels
 constexpr int kCompactThreads = 1024;
-constexpr int kSegsInFlight = 8;                  // 16-byte loads in flight per lane
-static_assert(16 % kSegsInFlight == 0, "a step never passes the 16th group of a chunk");
+constexpr int kCompactWaves = kCompactThreads / 64;
+constexpr int kRoundsInFlight = 8;                // 16-byte loads in flight per lane
 constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagPrefix = 2ull << 62;
 constexpr unsigned long long kValueMask = (1ull << 62) - 1;
@@ -168,6 +171,8 @@ __global__ __launch_bounds__(kCompactThreads) void reduce_compact_kernel(
     uint32_t *__restrict__ counts, unsigned long long *__restrict__ status,
     int32_t *__restrict__ n_unique, int32_t *__restrict__ err_flag) {
     __shared__ __align__(16) uint32_t hist[1 << kSliceBits];
+    // per wave: the rounds in flight' marks of where the lanes' pieces start
+    __shared__ uint8_t marks[kCompactWaves][64 * kRoundsInFlight];
     __shared__ uint32_t wave_tot[kCompactThreads / 64];
     __shared__ unsigned long long s_excl;
 
@@ -175,61 +180,77 @@ __global__ __launch_bounds__(kCompactThreads) void reduce_compact_kernel(
     const int lane = tid & 63, wave = tid >> 6;
     const int s = blockIdx.x;
 
+    // Lane l of wave w holds the word of tile c0 + kCompactWaves l + w of the
+    // tiles c0 .. c0 + 1023 (one pass of the block), so every wave has work
+    // however few tiles there are.  The first pass's words are requested
+    // before the histogram is cleared.
+    auto word_of = [&](int64_t c0) -> uint32_t {
+        const int64_t tw = c0 + kCompactWaves * lane + wave;
+        return tw < ntiles ? info[(size_t)s * ntiles + tw] : 0u;
+    };
+    uint32_t w = word_of(0);
     for (int i = tid * 4; i < (1 << kSliceBits); i += kCompactThreads * 4)
         *(uint4 *)(hist + i) = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = lane; i < 64 * kRoundsInFlight; i += 64) marks[wave][i] = 0u;
     __syncthreads();
 
-    // Segments are read 16 lanes to a segment (256 contiguous bytes per
-    // quarter-wave and step), four tiles per wave instruction.  The slice's
-    // (offset, count) words are loaded first, 1024 tiles at a time: in group
-    // i (tiles 64 i .. 64 i + 63 of the chunk) wave w takes tiles 64 i + 4 w
-    // + q, quarter q = 0..3, so that every wave has work however few tiles
-    // there are; lane 4 i + q of the wave holds that tile's word.  The loads
-    // of kSegsInFlight segments are in flight together.
-    {
-        const int q = lane >> 4, ql = lane & 15;
-        for (int64_t c0 = 0; c0 < ntiles; c0 += kCompactThreads) {
-            const int64_t tw = c0 + 64 * (lane >> 2) + 4 * wave + (lane & 3);
-            const uint32_t w = tw < ntiles ? info[(size_t)s * ntiles + tw] : 0u;
-            const int64_t left = ntiles - c0;
-            const int groups = left >= kCompactThreads ? 16 : (int)((left + 63) / 64);
-            // segment bounds are relative to the chunk's first key (at most
-            // 1024 tiles of 16384 keys: they fit 32 bits)
-            const uint16_t *kb = keys16 + (size_t)c0 * tile;
-            for (int i0 = 0; i0 < groups; i0 += kSegsInFlight) {
-                uint32_t s0[kSegsInFlight], s1[kSegsInFlight];
+    // Histogram.  The lane's segment [st, st + n) (key indices relative to
+    // the pass's first key: at most 1024 tiles of 16384 keys, so 32 bits)
+    // covers the 16-byte pieces st / 8 .. (st + n - 1) / 8; the wave lists
+    // all its lanes' pieces in lane order (an exclusive sum gives each lane
+    // where its own start) and takes them in rounds of 64, lane j piece
+    // q0 + j.  The lanes whose first piece falls in the rounds in flight
+    // mark it with 1 + their lane; a running maximum over the wave, carried
+    // from round to round, then gives each piece its segment.  A wave's LDS
+    // operations take effect in issue order, and signal fences keep the
+    // compiler from reordering them.
+    for (int64_t c0 = 0; c0 < ntiles; c0 += 64 * kCompactWaves) {
+        if (c0 != 0) w = word_of(c0);
+        const uint16_t *kb = keys16 + (size_t)c0 * tile;
+        const uint32_t st = (uint32_t)(kCompactWaves * lane + wave) * (uint32_t)tile + (w >> 16);
+        const uint32_t n = w & 0xFFFFu;
+        const uint32_t pieces = n ? ((st + n - 1u) >> 3) - (st >> 3) + 1u : 0u;
+        const uint32_t incl = wave_incl_sum(pieces);
+        const uint32_t excl = incl - pieces;
+        const uint32_t total = wave_last_u32(incl);
+        uint32_t carry = 0u;
+        for (uint32_t q0 = 0; q0 < total; q0 += 64 * kRoundsInFlight) {  // wave-uniform
+            const bool mark = pieces != 0u && excl >= q0 && excl < q0 + 64 * kRoundsInFlight;
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            if (mark) marks[wave][excl - q0] = (uint8_t)(lane + 1);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            uint32_t hq[kRoundsInFlight];
 #pragma unroll
-                for (int u = 0; u < kSegsInFlight; ++u) {
-                    const int i = i0 + u;
-                    const uint32_t wu = (uint32_t)__shfl((int)w, 4 * i + q, 64);  // 0 past the end
-                    const uint32_t t = (uint32_t)(64 * i + 4 * wave + q);
-                    s0[u] = t * (uint32_t)tile + (wu >> 16);
-                    s1[u] = s0[u] + (wu & 0xFFFFu);
-                }
-                for (uint32_t win = 0;; win += 128) {
-                    bool any = false;
+            for (int r = 0; r < kRoundsInFlight; ++r) hq[r] = marks[wave][64 * r + lane];
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            if (mark) marks[wave][excl - q0] = 0u;
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            uint32_t a[kRoundsInFlight], lo[kRoundsInFlight], hi[kRoundsInFlight];
+            uint4 v[kRoundsInFlight];
 #pragma unroll
-                    for (int u = 0; u < kSegsInFlight; ++u)
-                        any = any || ((s0[u] & ~7u) + win < s1[u]);
-                    if (__ballot(any) == 0ull) break;  // wave-uniform exit
-                    uint4 v[kSegsInFlight];
-                    uint32_t a[kSegsInFlight];
+            for (int r = 0; r < kRoundsInFlight; ++r) {
+                uint32_t o1 = wave_incl_max(hq[r]);
+                o1 = o1 > carry ? o1 : carry;
+                carry = wave_last_u32(o1);
+                const int o = o1 ? (int)o1 - 1 : 0;
+                const uint32_t st_o = (uint32_t)__shfl((int)st, o, 64);
+                const uint32_t n_o = (uint32_t)__shfl((int)n, o, 64);
+                const uint32_t ex_o = (uint32_t)__shfl((int)excl, o, 64);
+                const uint32_t q = q0 + 64 * r + lane;
+                const bool act = q < total;
+                a[r] = ((st_o >> 3) + (q - ex_o)) << 3;
+                lo[r] = act ? st_o : 0u;
+                hi[r] = act ? st_o + n_o : 0u;
+                v[r] = act ? *(const uint4 *)(kb + a[r]) : make_uint4(0u, 0u, 0u, 0u);
+            }
 #pragma unroll
-                    for (int u = 0; u < kSegsInFlight; ++u) {
-                        a[u] = (s0[u] & ~7u) + win + 8 * ql;
-                        v[u] = a[u] < s1[u] ? *(const uint4 *)(kb + a[u]) : make_uint4(0, 0, 0, 0);
-                    }
+            for (int r = 0; r < kRoundsInFlight; ++r) {
+                const uint32_t wd[4] = {v[r].x, v[r].y, v[r].z, v[r].w};
 #pragma unroll
-                    for (int u = 0; u < kSegsInFlight; ++u) {
-                        if (i0 + u >= groups) break;  // block-uniform: no tiles left
-                        const uint32_t wd[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) {
-                            const uint32_t pos = a[u] + e;
-                            if (pos >= s0[u] && pos < s1[u])
-                                atomicAdd(&hist[(wd[e >> 1] >> (16 * (e & 1))) & 0xFFFFu], 1u);
-                        }
-                    }
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t pos = a[r] + e;
+                    if (pos >= lo[r] && pos < hi[r])
+                        atomicAdd(&hist[(wd[e >> 1] >> (16 * (e & 1))) & 0xFFFFu], 1u);
                 }
             }
         }

@@ -111,6 +111,32 @@ def test_reduce_more_tiles_than_one_chunk():
     assert int(rn.sum()) == img.shape[0] * img.shape[1]
 
 
+@pytest.mark.parametrize("case", ["one_color_2^24", "one_color_2^25", "pair_2^24", "8200x4096"])
+def test_reduce_heavy_bins_and_many_tiles(case):
+    # Bins far past 2^16 pixels: one color filling 4096x4096 and 8192x4096
+    # images (2048 tiles, two passes of the compaction's tile words), two
+    # colors whose keys differ in the last bit (neighbouring bins), and a
+    # 33.6M-pixel image of 2051 tiles whose last pass holds 3 tiles.
+    wsm = _wsm()
+    if case == "one_color_2^24":
+        img = np.full((4096, 4096, 3), (17, 140, 201), dtype=np.uint8)
+    elif case == "one_color_2^25":
+        img = np.full((8192, 4096, 3), (250, 3, 98), dtype=np.uint8)
+    elif case == "pair_2^24":
+        img = np.zeros((4096, 4096, 3), dtype=np.uint8)
+        img[:] = (40, 200, 30)
+        img[1::2, :, 2] = 31
+        img[::7, ::3] = (40, 200, 31)
+    else:
+        big = synth.workload_image("large", 0)
+        img = np.concatenate([big, big[::-1][:4104]], axis=0)
+    _say("reduce", case, img.shape)
+    col, cnt = wsm.reduce_colors(_gpu_img(img))
+    rc, rn = oracle.reduce_colors(img)
+    assert np.array_equal(_u32(col), rc) and np.array_equal(_u32(cnt), rn)
+    assert int(rn.sum()) == img.shape[0] * img.shape[1]
+
+
 # ---------------------------------------------------------------------------
 # Iterations, lock-step.  The GPU keeps every center in float64 as well (the
 # correctly rounded mean of its exact integer sums) and decides every choice
