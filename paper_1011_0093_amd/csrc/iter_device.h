@@ -326,8 +326,8 @@ template <bool PACKED, bool FULL, bool DEFER, bool TAB = false>
 __device__ void search_chunk(const IterArgs &a, int i, int vb, int mode, const float4 *cen,
                              const double4 *cen64, const uint8_t *Ms, unsigned long long *acc,
                              double *dscr, unsigned long long *uscr, DeferQueue *dq,
-                             uint32_t (&key)[kCpt], uint32_t (&cnt)[kCpt], int (&pm)[kCpt],
-                             bool first = false, const float *Dd = nullptr,
+                             uint32_t *next, uint32_t (&key)[kCpt], uint32_t (&cnt)[kCpt],
+                             int (&pm)[kCpt], bool first = false, const float *Dd = nullptr,
                              FlatScratch *fs = nullptr, const float4 *Tb = nullptr, int ts = 0) {
     constexpr int NT = kSearchThreads;
     constexpr int NW = NT / 64;
@@ -337,32 +337,55 @@ __device__ void search_chunk(const IterArgs &a, int i, int vb, int mode, const f
     const int64_t ns = block_slots(a, vb);
     double sse = 0.0;
     uint32_t ev = 0;
-    for (int64_t s0 = 0; s0 < ns; s0 += kCpt * NW) {
-        if (s0 != 0) {
-#pragma unroll
-            for (int r = 0; r < kCpt; ++r) {
-                const int64_t slot = s0 + r * NW + wave;
-                const int64_t idx = slot_point(a, vb, slot);
-                if (slot < ns && idx < a.pts.n) {
-                    load_point(a.pts, idx, key[r], cnt[r]);
-                    pm[r] = a.sv.m[idx];
-                }
-            }
+    // The wave's next slot past the first pass, taken from the block's
+    // counter, and its point (loaded one round ahead).
+    int64_t dslot = 0;
+    uint32_t kd = 0u, cd = 0u;
+    int pd = 0;
+    auto take = [&]() {
+        uint32_t t = 0u;
+        if ((tid & 63) == 0) t = atomicAdd(next, 1u);
+        dslot = kCpt * NW + (int64_t)__builtin_amdgcn_readfirstlane(t);
+        const int64_t idx = slot_point(a, vb, dslot);
+        kd = 0u;
+        cd = 0u;
+        pd = 0;
+        if (dslot < ns && idx < a.pts.n) {
+            load_point(a.pts, idx, kd, cd);
+            pd = a.sv.m[idx];
         }
-        // one round per step, the points rotated so that the round's point
-        // is element 0 (the loop body is not unrolled)
+    };
+    // One round per loop step: first the first pass's kCpt slots (r NW +
+    // wave, whose points came with key/cnt/pm and are rotated so that the
+    // round's point is element 0), then slots taken one at a time from the
+    // block's counter, so that waves whose points scan long take fewer of
+    // them.  The loop body is not unrolled.
 #pragma unroll 1
-        for (int r = 0; r < kCpt; ++r) {
-            const uint32_t kr = key[0], cr = cnt[0];
-            const int pr = pm[0];
+    for (int r = 0;; ++r) {
+        uint32_t kr, cr;
+        int pr;
+        int64_t slot;
+        if (r < kCpt) {
+            kr = key[0];
+            cr = cnt[0];
+            pr = pm[0];
 #pragma unroll
             for (int v = 0; v + 1 < kCpt; ++v) {
                 key[v] = key[v + 1];
                 cnt[v] = cnt[v + 1];
                 pm[v] = pm[v + 1];
             }
-            if (s0 + r * NW >= ns) break;  // block-uniform
-            const int64_t slot = s0 + r * NW + wave;
+            slot = (int64_t)r * NW + wave;
+            if (r == kCpt - 1 && slot < ns) take();
+        } else {
+            kr = kd;
+            cr = cd;
+            pr = pd;
+            slot = dslot;
+            if (slot < ns) take();
+        }
+        if (slot >= ns) break;  // wave-uniform; the slots a wave visits ascend
+        {
             const int64_t idx = slot_point(a, vb, slot);
             const bool valid = slot < ns && idx < a.pts.n;
             float x, y, z;
@@ -459,6 +482,7 @@ struct SearchLds {
     typename std::conditional<kDefer, DeferQueue, NoQueue>::type dq;
     double dscr[kSearchThreads / 64];
     unsigned long long uscr[kSearchThreads / 64];
+    uint32_t next;  // the block's slot counter past the first pass
 };
 
 template <int V>
@@ -559,6 +583,7 @@ __device__ void search_body(const IterArgs &a, int i, int vb, SearchLds<V> &L) {
         }
     }
     for (int c = tid; c < a.k * NACC; c += NT) L.acc[c] = 0ull;
+    if (tid == 0) L.next = 0u;
     if constexpr (DEFER) {
         if (tid == 0) L.dq.n = 0u;
     }
@@ -568,8 +593,8 @@ __device__ void search_body(const IterArgs &a, int i, int vb, SearchLds<V> &L) {
     // completed no step yet, i.e. every membership is still 0 (state init).
     const bool first = FIRST && rec.iters == 0;
     search_chunk<PACKED, false, DEFER, TAB>(a, i, vb, rec.mode, L.cen, L.cen64, L.Ms, L.acc,
-                                            L.dscr, L.uscr, queue_of(L), key, cnt, pm, first,
-                                            L.Dd, L.fs, L.Tb, kTableStride);
+                                            L.dscr, L.uscr, queue_of(L), &L.next, key, cnt, pm,
+                                            first, L.Dd, L.fs, L.Tb, kTableStride);
 }
 
 

@@ -78,6 +78,7 @@ __global__ __launch_bounds__(kSearchThreads) void fused_step_kernel(IterArgs a, 
     __shared__ float4 Tb[kFusedMaxK * kFusedMaxK];
     __shared__ double dscr[kSearchThreads / 64];
     __shared__ unsigned long long uscr[kSearchThreads / 64];
+    __shared__ uint32_t next;
     constexpr int NT = kSearchThreads;
     constexpr int NACC = PACKED ? 2 : 4;
     static_assert(kFusedMaxK * kFusedMaxK <= NT, "one thread per row entry");
@@ -103,6 +104,7 @@ __global__ __launch_bounds__(kSearchThreads) void fused_step_kernel(IterArgs a, 
               << 32) | (unsigned)t;
     }
     keys[tid] = kt;
+    if (tid == 0) next = 0u;
     __syncthreads();
     if (entry) {
         const ulonglong2 *k2 = (const ulonglong2 *)(keys + p * kFusedMaxK);
@@ -119,8 +121,8 @@ __global__ __launch_bounds__(kSearchThreads) void fused_step_kernel(IterArgs a, 
     // a fresh state (no step completed) starts from center 0 everywhere:
     // the full scan gives the same centers (see search_chunk)
     search_chunk<PACKED, false, false, true>(a, i, blockIdx.x, rec.mode, cen, cen64, Ms, acc, dscr,
-                                             uscr, nullptr, key, cnt, pm, rec.iters == 0, nullptr,
-                                             nullptr, Tb, kFusedMaxK);
+                                             uscr, nullptr, &next, key, cnt, pm, rec.iters == 0,
+                                             nullptr, nullptr, Tb, kFusedMaxK);
 }
 
 // Full-search comparator: one launch per step, the update applied
@@ -132,6 +134,7 @@ __global__ __launch_bounds__(kSearchThreads) void full_step_kernel(IterArgs a, i
     __shared__ unsigned long long acc[kMaxK * 4];
     __shared__ double dscr[kSearchThreads / 64];
     __shared__ unsigned long long uscr[kSearchThreads / 64];
+    __shared__ uint32_t next;
     constexpr int NT = kSearchThreads;
     constexpr int NACC = PACKED ? 2 : 4;
     const int tid = threadIdx.x;
@@ -144,9 +147,10 @@ __global__ __launch_bounds__(kSearchThreads) void full_step_kernel(IterArgs a, i
         clear_totals<NT, PACKED>(a.sv.totals + (size_t)((i + 1) % 3) * kTotSlot, a.k);
     }
     for (int c = tid; c < a.k * NACC; c += NT) acc[c] = 0ull;
+    if (tid == 0) next = 0u;
     __syncthreads();
     search_chunk<PACKED, true, false>(a, i, blockIdx.x, rec.mode, cen, cen64, nullptr, acc, dscr,
-                                      uscr, nullptr, key, cnt, pm);
+                                      uscr, nullptr, &next, key, cnt, pm);
 }
 
 // Final update after the last step of a call (one block).  Publishes the
