@@ -34,6 +34,7 @@ constexpr int kScanBatch = 8;                    // row entries fetched per scan
 static_assert(kScanBatch == 8, "a scan batch is one 8-byte word of a row, read aligned");
 static_assert(kMaxK % kScanBatch == 0, "a batched full scan stays inside the center table");
 constexpr int kRowPrefix = 64;                   // row head scanned flat (in LDS when scans defer)
+constexpr int kLaneHead = 16;                    // entries of the flat scan a lane takes itself
 static_assert(kRowPrefix == kRowDist, "the stored distances cover the LDS row prefix");
 constexpr int kDeferCap = 1024;                  // deferred scans per block
 constexpr int kDeferBatch = 8;                   // deferred scans a wave fetches rows for at once
@@ -458,7 +459,9 @@ struct FlatScratch {
 // within a wave, and a wave runs as long as its longest lane.
 //   Row p is ascending in d(c_p, c_t)^2, so the entries before the break are
 // the first n, n = the number of stored distances Dd[p][.] below the
-// threshold (a binary search).  The wave lists its (point, entry) pairs in
+// threshold (a binary search).  The first kLaneHead of them (most scans
+// end there) each lane evaluates itself, in row order.  The wave lists the
+// remaining (point, entry) pairs in
 // lane order and takes them in rounds of 64, lane l pair q0 + l of round q0;
 // it finds the pair's point from the marks of where each point's pairs start
 // (the lanes whose first pair falls in the round write them; a running
@@ -499,13 +502,46 @@ __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, in
     more = valid && n == L && L < K - 1;
     dj = n < L ? dr[n] : kNoSkip;
     prev_out = prev;
-    const uint32_t incl = wave_incl_sum((uint32_t)n);
-    const int excl = (int)incl - n;
+    // The first n1 = min(n, kLaneHead) pairs by the lane itself, in row
+    // order, each key folded into the lane's minimum and compared with the
+    // minimum it meets (the same rule as the dealt pairs below).
+    const int n1 = n < kLaneHead ? n : kLaneHead;
+    unsigned long long bk = scan_key(prev, pp, pp);
+    bool nr = false;
+    {
+        constexpr int kWords = kLaneHead < 8 ? 1 : kLaneHead / 8;  // 8-entry words of the row head
+        uint2 w8[kWords];
+#pragma unroll
+        for (int u = 0; u < kWords; ++u) w8[u] = ((const uint2 *)(Ms + pp * kRowPrefix))[u];
+#pragma unroll
+        for (int e = 0; e < kLaneHead; ++e) {
+            if (e < n1) {
+                const uint2 w = w8[e >> 3];
+                const int t = (int)((((e & 7) < 4 ? w.x : w.y) >> (8 * (e & 3))) & 0xFFu);
+                const float4 ct = cen[t];
+                const unsigned long long kq =
+                    scan_key(sq_dist(x, y, z, ct.x, ct.y, ct.z), t, -1);
+                nr = nr || near_pair(key_dist(kq), key_dist(bk));
+                bk = kq < bk ? kq : bk;
+            }
+        }
+    }
+    // The rest of the pairs, entries n1 .. n - 1, dealt over the wave.
+    const int n2 = n - n1;
+    const uint32_t incl = wave_incl_sum((uint32_t)n2);
+    const int excl = (int)incl - n2;
     const int total = (int)wave_last_u32(incl);
+    if (total == 0) {  // wave-uniform: every scan ended within its lane's part
+        bd = key_dist(bk);
+        s2 = nr ? bd : kNoSkip;
+        best = (bk & 0x100ull) ? (int)(bk & 0xFFull) : pp;
+        if (valid) ev += 1u + (uint32_t)n;
+        return;
+    }
     fs.head[lane] = 0u;
-    fs.pt[lane] = make_float4(x, y, z, __int_as_float(pp * kRowPrefix - excl));
-    fs.bk[lane] = scan_key(prev, pp, pp);
-    fs.near[lane] = 0u;
+    fs.pt[lane] = make_float4(x, y, z, __int_as_float(pp * kRowPrefix + n1 - excl));
+    fs.bk[lane] = bk;
+    fs.near[lane] = nr ? 1u : 0u;
     uint32_t carry = 0u;
     // A pair's key is compared with the minimum it met one iteration late,
     // so the wait for the returned value overlaps the next iteration's LDS
@@ -517,7 +553,7 @@ __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, in
         const bool act = q < total;
         // this round's marks: written, read, and cleared again by their
         // writers (a wave's LDS operations take effect in issue order)
-        const bool mark = n > 0 && excl >= q0 && excl < q0 + 64;
+        const bool mark = n2 > 0 && excl >= q0 && excl < q0 + 64;
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (mark) fs.head[excl - q0] = (uint8_t)(lane + 1);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
