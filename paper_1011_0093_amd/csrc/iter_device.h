@@ -474,8 +474,6 @@ struct SearchLds {
     unsigned long long acc[kMaxK * 4];
     // rows of M: the first kRowPrefix entries when scans defer, else whole
     __align__(16) uint8_t Ms[var_ms_bytes<V>()];
-    // kVarTable: the row tables (sm_scan_tab)
-    float4 Tb[V == kVarTable ? kTableMaxK * kTableStride : 1];
     // kVarDefer: the distances of the row heads, and the flat scans' scratch
     __align__(16) float Dd[kDefer ? kMaxK * kRowDist : 4];
     FlatScratch fs[kDefer ? kSearchThreads / 64 : 1];
@@ -516,8 +514,7 @@ __device__ void rows_body(const IterArgs &a, int i, int p0, int p1, RowsLds &L) 
     }
     for (int p = p0; p < p1; ++p)
         sort_row<kSortThreads>(L.cen, a.k, p, L.keys, L.rank, a.sv.rows + (size_t)p * kRowStride,
-                               a.sv.rowd + (size_t)p * kRowDist,
-                               a.k <= kTableMaxK ? a.sv.rowt + (size_t)p * kTableStride : nullptr);
+                               a.sv.rowd + (size_t)p * kRowDist);
 }
 
 // Sort-means step i, search part (kSearchThreads threads), block vb of
@@ -526,7 +523,7 @@ template <bool PACKED, int V>
 __device__ void search_body(const IterArgs &a, int i, int vb, SearchLds<V> &L) {
     constexpr int NT = kSearchThreads;
     constexpr int NACC = PACKED ? 2 : 4;
-    constexpr bool DEFER = V == kVarDefer, FIRST = V == kVarFirst, TAB = V == kVarTable;
+    constexpr bool DEFER = V == kVarDefer, FIRST = V == kVarFirst;
     const int tid = threadIdx.x;
     uint32_t key[kCpt], cnt[kCpt];
     int pm[kCpt];
@@ -550,29 +547,11 @@ __device__ void search_body(const IterArgs &a, int i, int vb, SearchLds<V> &L) {
                                                : make_uint4(0u, 0u, 0u, 0u);
         }
     }
-    // kVarTable: the row tables the rows launch wrote
-    constexpr int kTbRegs = TAB ? kTableMaxK * kTableStride / NT : 1;
-    static_assert(!TAB || kTableMaxK * kTableStride == kTbRegs * NT, "table copy");
-    float4 treg[kTbRegs];
-    if (TAB) {
-#pragma unroll
-        for (int u = 0; u < kTbRegs; ++u) {
-            const int q = tid + u * NT;
-            treg[u] = q < a.k * kTableStride ? a.sv.rowt[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-    }
     const Record rec = a.sv.hdr->rec[(i + 1) & 1];
     if (rec.converged) return;
     if (tid < a.k) {
         L.cen[tid] = pc;
         L.cen64[tid] = pc64;
-    }
-    if (TAB) {
-#pragma unroll
-        for (int u = 0; u < kTbRegs; ++u) {
-            const int q = tid + u * NT;
-            if (q < a.k * kTableStride) L.Tb[q] = treg[u];
-        }
     }
     store_rows<NT, DEFER>(R, a.k, L.Ms);
     if (DEFER) {
@@ -592,9 +571,9 @@ __device__ void search_body(const IterArgs &a, int i, int vb, SearchLds<V> &L) {
     // The launch for a call's first step (FIRST) checks whether the state has
     // completed no step yet, i.e. every membership is still 0 (state init).
     const bool first = FIRST && rec.iters == 0;
-    search_chunk<PACKED, false, DEFER, TAB>(a, i, vb, rec.mode, L.cen, L.cen64, L.Ms, L.acc,
-                                            L.dscr, L.uscr, queue_of(L), &L.next, key, cnt, pm,
-                                            first, L.Dd, L.fs, L.Tb, kTableStride);
+    search_chunk<PACKED, false, DEFER>(a, i, vb, rec.mode, L.cen, L.cen64, L.Ms, L.acc, L.dscr,
+                                       L.uscr, queue_of(L), &L.next, key, cnt, pm, first, L.Dd,
+                                       L.fs);
 }
 
 

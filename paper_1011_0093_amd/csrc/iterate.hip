@@ -12,10 +12,10 @@
 //      (Sec. 2: the inter-center distances with every row sorted).
 // Step i, search launch (one block per chunk of points):
 //   3. sort-means from each point's previous center over an LDS copy of M
-//      (the launch variants kVar* of sm_block.h: for K <= kTableMaxK with
-//      the row tables, for K >= kDeferMinK a wave's scans over the row
-//      heads spread over its lanes and the rare longer ones finished by
-//      whole waves);
+//      (the launch variants kVar* of sm_block.h: after a call's first step,
+//      each lane scans the first entries of its point's row, a wave's
+//      further scans over the row heads are spread over its lanes and the
+//      rare longer ones finished by whole waves);
 //   4. sums count * (R, G, B, 1) per center: runs of equal centers within a
 //      wave are pre-summed with a segmented scan, then added into LDS, and
 //      each block flushes its non-zero sums with 64-bit device atomics into
@@ -368,10 +368,9 @@ static int launch_steps(const IterArgs &a, int max_iters, bool full, hipStream_t
         } else {
             WSM_LAUNCH(WSM_KERNEL_ROWS, rows_kernel<PACKED>, dim3(a.k), dim3(kSortThreads), stream,
                        a, i);
-            const auto search = i == 0                ? search_kernel<PACKED, kVarFirst>
-                                : a.k >= kDeferMinK   ? search_kernel<PACKED, kVarDefer>
-                                : a.k <= kTableMaxK   ? search_kernel<PACKED, kVarTable>
-                                                      : search_kernel<PACKED, kVarLane>;
+            // K >= kDeferMinK here
+            const auto search =
+                i == 0 ? search_kernel<PACKED, kVarFirst> : search_kernel<PACKED, kVarDefer>;
             WSM_LAUNCH(WSM_KERNEL_SEARCH, search, dim3(a.grid), dim3(kSearchThreads), stream, a,
                        i);
         }

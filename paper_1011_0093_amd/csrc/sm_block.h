@@ -6,20 +6,21 @@
 // left out, since the scan starts from the second one.  It is built once per
 // set of centers (sort_row, one block per row) and kept in device memory as
 // K rows of kRowStride bytes, with the distances of each row's first
-// kRowDist entries and, for K <= kTableMaxK, row tables (entry j of row p as
-// (c_t, d(c_p, c_t)^2)); a search block copies the rows (for K >= kDeferMinK
-// only their first kRowPrefix entries and those distances, for K <=
-// kTableMaxK with the tables) into LDS.  (For K <= kFusedMaxK every search
-// block sorts the rows itself.)  A scan compares d(c_p, c_t)^2 recomputed
-// from the centers in LDS, or the stored value, with the same expression the
-// rows were sorted by, so the break test sees bit-equal values.
+// kRowDist entries; a search block copies the rows (for K >= kDeferMinK
+// only their first kRowPrefix entries and those distances) into LDS.  (For
+// K <= kFusedMaxK every search block sorts the rows itself, with a row
+// table: entry j of row p as (c_t, d(c_p, c_t)^2).)  A scan compares
+// d(c_p, c_t)^2 recomputed from the centers in LDS, or the stored value,
+// with the same expression the rows were sorted by, so the break test sees
+// bit-equal values.
 //
 // For K < kDeferMinK a lane scans its own point's row, kScanBatch entries
-// at a time (sm_scan, or sm_scan_tab over the row tables).  For K >=
-// kDeferMinK a wave scans the row heads of its 64 points together, with the
-// entries dealt out evenly over the lanes (sm_scan_flat), and the rare scans
-// that go past the head are finished by the whole wave (sm_finish_wave), so
-// that no lane holds its wave.
+// at a time (sm_scan, or sm_scan_tab over a row table).  For K >=
+// kDeferMinK each lane scans the first kLaneHead entries of its point's row
+// and a wave then takes the rest of its 64 points' row heads together, with
+// the entries dealt out evenly over the lanes (sm_scan_flat), and the rare
+// scans that go past the head are finished by the whole wave
+// (sm_finish_wave), so that no lane holds its wave.
 #pragma once
 
 #include "wave_ops.h"
@@ -38,11 +39,9 @@ constexpr int kLaneHead = 16;                    // entries of the flat scan a l
 static_assert(kRowPrefix == kRowDist, "the stored distances cover the LDS row prefix");
 constexpr int kDeferCap = 1024;                  // deferred scans per block
 constexpr int kDeferBatch = 8;                   // deferred scans a wave fetches rows for at once
-constexpr int kDeferMinK = 128;                  // smallest K whose search defers
+constexpr int kDeferMinK = 33;                   // smallest K whose search scans flat
 constexpr int kFusedMaxK = 32;                   // largest K sorted inside the search block
-constexpr int kTableMaxK = kRowTabRows;          // largest K whose search keeps row tables
-constexpr int kTableStride = kRowTabStride;      // entries per row of a row table
-static_assert(kTableMaxK - 1 <= kTableStride, "a table row holds the whole row of M");
+static_assert(kDeferMinK == kFusedMaxK + 1, "the launches past the fused kernel scan flat");
 
 // LDS row stride for K centers: K - 1 entries rounded up to 16 bytes.
 __host__ __device__ constexpr int lds_row_stride(int K) { return ((K - 1) + 15) / 16 * 16; }
@@ -68,13 +67,11 @@ __device__ __forceinline__ bool run_tail(int key, bool valid) {
 // their bit patterns order like the values, and the keys are distinct.  The
 // rank of each key is counted by NT / kMaxK threads over slices of the
 // others.  If drow is not null, the distances of the first kRowDist entries
-// are written to it as well, and if trow is not null the row table (entry j
-// as (c_t, d(c_p, c_t)^2), for K <= kRowTabRows).  All NT threads call it;
-// it starts with a barrier, so consecutive calls may reuse the scratch.
+// are written to it as well.  All NT threads call it; it starts with a
+// barrier, so consecutive calls may reuse the scratch.
 template <int NT>
 __device__ void sort_row(const float4 *cen, int K, int p, unsigned long long *__restrict__ keys,
-                         uint32_t *rank, uint8_t *__restrict__ row, float *__restrict__ drow,
-                         float4 *__restrict__ trow = nullptr) {
+                         uint32_t *rank, uint8_t *__restrict__ row, float *__restrict__ drow) {
     static_assert(NT % kMaxK == 0, "block size");
     constexpr int Q = NT / kMaxK;
     constexpr int span = kMaxK / Q;
@@ -117,12 +114,8 @@ __device__ void sort_row(const float4 *cen, int K, int p, unsigned long long *__
         if (c != p) {
             const uint32_t rk = rank[c];
             row[rk] = (uint8_t)c;
-            const float d = __uint_as_float((uint32_t)(keys[c] >> 32));
-            if (drow && rk < (uint32_t)kRowDist) drow[rk] = d;
-            if (trow) {
-                const float4 ct = cen[c];
-                trow[rk] = make_float4(ct.x, ct.y, ct.z, d);
-            }
+            if (drow && rk < (uint32_t)kRowDist)
+                drow[rk] = __uint_as_float((uint32_t)(keys[c] >> 32));
         }
     }
 }
@@ -677,20 +670,17 @@ struct NoQueue {};
 // How a search launch holds M in LDS and scans it:
 //   kVarFirst: whole rows (a call's first step: the full scan on a fresh
 //              state, else sm_scan);
-//   kVarLane:  whole rows, sm_scan;
-//   kVarTable: K <= kTableMaxK, whole rows and their row tables, sm_scan_tab;
+//   kVarLane:  whole rows, sm_scan (the batched form's steps for K <
+//              kDeferMinK);
 //   kVarDefer: K >= kDeferMinK, the row heads and their distances, flat
 //              scans (sm_scan_flat), longer scans deferred.
 constexpr int kVarFirst = 0;
 constexpr int kVarLane = 1;
-constexpr int kVarTable = 2;
 constexpr int kVarDefer = 3;
 // LDS bytes of M for a variant
 template <int V>
 constexpr int var_ms_bytes() {
-    return V == kVarDefer ? kMaxK * kRowPrefix
-                          : V == kVarTable ? kTableMaxK * lds_row_stride(kTableMaxK)
-                                           : kMaxK * kRowStride;
+    return V == kVarDefer ? kMaxK * kRowPrefix : kMaxK * kRowStride;
 }
 
 // Finishes a block's deferred scans (Ms holds row heads of kRowPrefix

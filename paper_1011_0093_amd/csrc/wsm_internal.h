@@ -90,11 +90,7 @@ constexpr size_t kOffMapPart = kOffEvalHist + kHistory * 8;           // double[
 constexpr size_t kOffRows = align_up(kOffMapPart + kMaxGrid * 8, 256);  // u8[256][256]
 constexpr int kRowDist = 64;  // leading entries of each row whose distances are kept
 constexpr size_t kOffRowDist = kOffRows + (size_t)kMaxK * kMaxK;  // float[256][kRowDist]
-// row tables for K <= kRowTabRows: entry j of row p as (c_t, d(c_p, c_t)^2)
-constexpr int kRowTabRows = 64;
-constexpr int kRowTabStride = 64;
-constexpr size_t kOffRowTab = kOffRowDist + (size_t)kMaxK * kRowDist * 4;  // float4[64][64]
-constexpr size_t kOffMembership = kOffRowTab + (size_t)kRowTabRows * kRowTabStride * 16;
+constexpr size_t kOffMembership = kOffRowDist + (size_t)kMaxK * kRowDist * 4;
 
 inline size_t state_bytes_for(int64_t n_points) {
     return kOffMembership + align_up((size_t)n_points, 256);
@@ -113,7 +109,6 @@ struct StateView {
     double *map_part;     // [kMaxGrid]
     uint8_t *rows;        // [256][256]: sorted neighbour rows (M without self)
     float *rowd;          // [256][kRowDist]: d(c_p, c_t)^2 of the first entries of row p
-    float4 *rowt;         // [kRowTabRows][kRowTabStride]: row tables (small K)
     uint8_t *m;           // [n_points]
 };
 
@@ -131,7 +126,6 @@ inline StateView make_view(void *state) {
     v.map_part = (double *)(b + kOffMapPart);
     v.rows = (uint8_t *)(b + kOffRows);
     v.rowd = (float *)(b + kOffRowDist);
-    v.rowt = (float4 *)(b + kOffRowTab);
     v.m = (uint8_t *)(b + kOffMembership);
     return v;
 }

@@ -225,12 +225,13 @@ def test_lockstep_medium(K):
     print(stats[-1])
 
 
-@pytest.mark.parametrize("K", [2, 31, 63, 65, 97, 127, 128, 129, 200, 255])
+@pytest.mark.parametrize("K", [2, 17, 31, 33, 63, 65, 66, 97, 127, 128, 200, 255])
 def test_lockstep_k_around_kernel_switches(K):
-    # K <= 32: one fused launch; 33..64: rows + lane scans over row tables;
-    # 65..127: rows + lane scans; >= 128: rows + flattened scans over 64-entry
-    # heads with deferral.  Odd K give rows whose length is not a multiple of
-    # the scan batch or of the head.
+    # K <= 32: one fused launch with lane scans (K = 17: rows of 16 entries);
+    # K >= 33: rows + per-lane scans of the first 16 entries, then flattened
+    # scans over 64-entry row heads; up to K = 65 the head holds the whole
+    # row, from K = 66 on a scan can go past it and is deferred.  Odd K give
+    # rows whose length is not a multiple of the scan batch or of the head.
     img = synth.workload_image("medium", 1)
     _say("lockstep medium seed 1 K", K)
     stats = _lockstep(img, K, 1, 4)
