@@ -54,11 +54,11 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
     __shared__ FlatScratch fs[FLAT ? NW : 1];
     __shared__ DeferQueue dq;
     __shared__ double dscr[NW];
+    __shared__ uint32_t next;  // the block's next slot
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     // the 64-color chunks b, b + grid, b + 2 grid, ... (every block samples
-    // the whole key range, so the blocks get similar work); wave w takes
-    // chunk slot s0 + r * NW + w of pass s0
+    // the whole key range, so the blocks get similar work), its slots
     const int64_t grid = gridDim.x;
     const int64_t chunks = (n + 63) / 64;
     const int64_t ns = chunks > (int64_t)blockIdx.x ? (chunks - blockIdx.x + grid - 1) / grid : 0;
@@ -75,42 +75,44 @@ __global__ __launch_bounds__(kSearchThreads) void map_assign_kernel(
     if (FLAT)
         for (int q = tid; q < K * (kRowDist / 4); q += NT)
             ((uint4 *)Dd)[q] = ((const uint4 *)sv.rowd)[q];
-    if (tid == 0) dq.n = 0u;
+    if (tid == 0) {
+        dq.n = 0u;
+        next = 0u;
+    }
     const int mode = block_mode(flags);
     double acc = 0.0;
     uint32_t ev = 0;
-    for (int64_t s0 = 0; s0 < ns; s0 += kCpt * NW) {
-        uint32_t key[kCpt], cnt[kCpt];
-        int pm[kCpt];
-#pragma unroll
-        for (int r = 0; r < kCpt; ++r) {
-            const int64_t slot = s0 + r * NW + wave;
-            const int64_t idx = ((int64_t)blockIdx.x + slot * grid) * 64 + lane;
-            key[r] = 0u;
-            cnt[r] = 0u;
-            pm[r] = 0;
-            if (slot < ns && idx < n) {
-                key[r] = colors[idx];
-                cnt[r] = counts[idx];
-                pm[r] = sv.m[idx];
-            }
+    // Each wave takes the block's slots one at a time from an LDS counter,
+    // the next slot's colors loaded a round ahead, so that waves whose
+    // colors scan long take fewer slots.
+    int64_t dslot = 0;
+    uint32_t kd = 0u, cd = 0u;
+    int pd = 0;
+    auto take = [&]() {
+        uint32_t t = 0u;
+        if (lane == 0) t = atomicAdd(&next, 1u);
+        dslot = (int64_t)__builtin_amdgcn_readfirstlane(t);
+        const int64_t idx = ((int64_t)blockIdx.x + dslot * grid) * 64 + lane;
+        kd = 0u;
+        cd = 0u;
+        pd = 0;
+        if (dslot < ns && idx < n) {
+            kd = colors[idx];
+            cd = counts[idx];
+            pd = sv.m[idx];
         }
-        // one round per step, the points rotated so that the round's point
-        // is element 0 (the loop body is not unrolled)
+    };
+    take();
 #pragma unroll 1
-        for (int r = 0; r < kCpt; ++r) {
-            const uint32_t kr = key[0], cr = cnt[0];
-            const int pr = pm[0];
-#pragma unroll
-            for (int v = 0; v + 1 < kCpt; ++v) {
-                key[v] = key[v + 1];
-                cnt[v] = cnt[v + 1];
-                pm[v] = pm[v + 1];
-            }
-            if (s0 + r * NW >= ns) break;  // block-uniform
-            const int64_t slot = s0 + r * NW + wave;
+    for (;;) {
+        const uint32_t kr = kd, cr = cd;
+        const int pr = pd;
+        const int64_t slot = dslot;
+        if (slot >= ns) break;  // wave-uniform
+        take();
+        {
             const int64_t idx = ((int64_t)blockIdx.x + slot * grid) * 64 + lane;
-            const bool valid = slot < ns && idx < n;
+            const bool valid = idx < n;
             // the wave's scans over the row heads together; one that goes
             // past the head is deferred (or, with the queue full, carried on
             // by its lane)
