@@ -1,5 +1,7 @@
 // Iterations of the weighted sort-means loop (Alg. 2) on gfx950: two
-// launches per iteration (one for the full-search comparator).
+// launches per iteration for K > kFusedMaxK, one for smaller K (the fused
+// kernel sorts the rows inside every search block) and for the full-search
+// comparator.
 //
 // Step i, rows launch (one block per center p):
 //   1. every block applies the center update of step i-1 (Alg. 2, last
@@ -10,7 +12,8 @@
 //      palette and the record;
 //   2. block p sorts row p of the neighbour matrix M for the new centers
 //      (Sec. 2: the inter-center distances with every row sorted).
-// Step i, search launch (one block per chunk of points):
+// Step i, search launch (each block takes the 64-color chunks b, b + grid,
+// ...; its waves take them one at a time from an LDS counter):
 //   3. sort-means from each point's previous center over an LDS copy of M
 //      (the launch variants kVar* of sm_block.h: after a call's first step,
 //      each lane scans the first entries of its point's row, a wave's
