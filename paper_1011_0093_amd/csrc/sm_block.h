@@ -496,28 +496,37 @@ __device__ __forceinline__ void sm_scan_flat(bool valid, uint32_t key, int p, in
     dj = n < L ? dr[n] : kNoSkip;
     prev_out = prev;
     // The first n1 = min(n, kLaneHead) pairs by the lane itself, in row
-    // order, each key folded into the lane's minimum and compared with the
-    // minimum it meets (the same rule as the dealt pairs below).
+    // order, as in sm_scan: the best (tie rule of better_center, the same
+    // order as scan_key's) and the second smallest distance s2 among the
+    // evaluated centers, the previous one included.  Its near-tie flag is
+    // then whether s2 is near the best: near_pair is monotone in the larger
+    // distance, so that covers every evaluated center.
     const int n1 = n < kLaneHead ? n : kLaneHead;
-    unsigned long long bk = scan_key(prev, pp, pp);
-    bool nr = false;
+    unsigned long long bk;
+    bool nr;
     {
         constexpr int kWords = kLaneHead < 8 ? 1 : kLaneHead / 8;  // 8-entry words of the row head
         uint2 w8[kWords];
 #pragma unroll
         for (int u = 0; u < kWords; ++u) w8[u] = ((const uint2 *)(Ms + pp * kRowPrefix))[u];
+        float hb = prev, hs2 = kNoSkip;
+        int hbest = pp;
 #pragma unroll
         for (int e = 0; e < kLaneHead; ++e) {
             if (e < n1) {
                 const uint2 w = w8[e >> 3];
                 const int t = (int)((((e & 7) < 4 ? w.x : w.y) >> (8 * (e & 3))) & 0xFFu);
-                const float4 ct = cen[t];
-                const unsigned long long kq =
-                    scan_key(sq_dist(x, y, z, ct.x, ct.y, ct.z), t, -1);
-                nr = nr || near_pair(key_dist(kq), key_dist(bk));
-                bk = kq < bk ? kq : bk;
+                const float3 ct = *(const float3 *)(cen + t);  // the 4th lane is unused
+                const float d = sq_dist(x, y, z, ct.x, ct.y, ct.z);
+                hs2 = fminf(hs2, fmaxf(d, hb));
+                if (better_center(d, hb, t, hbest, pp)) {
+                    hb = d;
+                    hbest = t;
+                }
             }
         }
+        bk = scan_key(hb, hbest, pp);
+        nr = hs2 < kNoSkip && near_pair(hs2, hb);
     }
     // The rest of the pairs, entries n1 .. n - 1, dealt over the wave.
     const int n2 = n - n1;
