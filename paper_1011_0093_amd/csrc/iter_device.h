@@ -314,9 +314,9 @@ __device__ void finish_block(const IterArgs &a, int i, int vb, int mode, const f
     }
 }
 
-// Search and accumulation over a block's points (block_slots), in passes of
-// kPass (kCpt points per thread); the first pass's points are already in
-// key/cnt/pm.  Sort-means over the LDS copy Ms of M, or full
+// Search and accumulation over a block's points (block_slots): a first
+// pass of kCpt 64-color slots per wave, whose points are already in
+// key/cnt/pm, then slots taken one at a time from the block's counter.  Sort-means over the LDS copy Ms of M, or full
 // search for the comparator (Ms unused); every choice is then made final in
 // float64 by decide64 (mode: of the centers cen, whose float64 values are
 // cen64), and the SSE is summed from float64 distances.  Adds the block's

@@ -28,8 +28,8 @@
 
 namespace wsm {
 
-constexpr int kCpt = 4;                          // points per thread per pass
-constexpr int kPass = kSearchThreads * kCpt;     // points per pass (4096)
+constexpr int kCpt = 2;                          // points per thread of a search block's first pass
+constexpr int kPass = 4096;                      // points per block and pass of the default grid rule
 constexpr int kRowStride = kMaxK;                // bytes per row of M in device memory
 constexpr int kScanBatch = 8;                    // row entries fetched per scan step
 static_assert(kScanBatch == 8, "a scan batch is one 8-byte word of a row, read aligned");
