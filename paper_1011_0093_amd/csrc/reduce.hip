@@ -35,7 +35,7 @@ constexpr int kMaxPpt = 16;                       // pixels per thread (max)
 constexpr int kMaxTile = kPartThreads * kMaxPpt;  // 16384 pixels
 constexpr int kCompactThreads = 1024;
 constexpr int kCompactWaves = kCompactThreads / 64;
-constexpr int kRoundsInFlight = 8;                // 16-byte loads in flight per lane
+constexpr int kRoundsInFlight = 2;                // 16-byte loads in flight per lane
 constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagPrefix = 2ull << 62;
 constexpr unsigned long long kValueMask = (1ull << 62) - 1;
