@@ -9,7 +9,8 @@
 //              slices gives every pixel a rank; the low keys are written out
 //              grouped by slice (a tile-local counting sort), 2 bytes per
 //              pixel with 16-byte stores, together with an (offset, count)
-//              word per (slice, tile).
+//              word per (slice, tile).  The blocks of one XCD take
+//              consecutive tiles (xcd_tile).
 //   compact    one block per slice.  Each wave takes the slice's segments
 //              in a set of tiles (one (offset, count) word per lane), lays
 //              them end to end as a list of 16-byte pieces and deals the
@@ -62,6 +63,18 @@ constexpr ReduceLayout reduce_layout(int64_t n) {
     return L;
 }
 
+// Tile of partition block blk.  Workgroups are dealt to the 8 XCDs in turn,
+// so the blocks of one XCD (equal blk mod 8) take a consecutive run of tiles:
+// each line of a slice's (offset, count) words is then written whole by one
+// XCD's L2.  The grid is ntiles rounded up to a multiple of 8; a block left
+// without a tile returns ntiles.
+__device__ __forceinline__ int64_t xcd_tile(int64_t blk, int64_t ntiles) {
+    const int64_t x = blk & 7, j = blk >> 3;
+    const int64_t q = ntiles >> 3, r = ntiles & 7;
+    const int64_t cnt = q + (x < r ? 1 : 0);
+    return j < cnt ? x * q + (x < r ? x : r) + j : ntiles;
+}
+
 // ---------------------------------------------------------------------------
 template <bool VEC16>
 __global__ __launch_bounds__(kPartThreads) void reduce_partition_kernel(
@@ -75,7 +88,8 @@ __global__ __launch_bounds__(kPartThreads) void reduce_partition_kernel(
     __shared__ uint32_t wave_tot[kPartThreads / 64];
 
     const int tid = threadIdx.x;
-    const int64_t b = blockIdx.x;
+    const int64_t b = xcd_tile(blockIdx.x, ntiles);
+    if (b >= ntiles) return;
     const int64_t base = b * (int64_t)tile;
     const int len = (int)((n - base) < tile ? (n - base) : tile);
 
@@ -390,11 +404,11 @@ static int reduce_launch(const uint8_t *rgb, int64_t n_pixels, uint32_t *colors,
     (void)hipGetLastError();
     if (vec)
         WSM_LAUNCH(WSM_KERNEL_REDUCE_PARTITION, reduce_partition_kernel<true>,
-                   dim3((unsigned)L.ntiles), dim3(kPartThreads), stream, rgb, n_pixels, L.ppt,
+                   dim3((unsigned)((L.ntiles + 7) & ~7ll)), dim3(kPartThreads), stream, rgb, n_pixels, L.ppt,
                    L.tile, L.ntiles, keys16, info, status, err);
     else
         WSM_LAUNCH(WSM_KERNEL_REDUCE_PARTITION, reduce_partition_kernel<false>,
-                   dim3((unsigned)L.ntiles), dim3(kPartThreads), stream, rgb, n_pixels, L.ppt,
+                   dim3((unsigned)((L.ntiles + 7) & ~7ll)), dim3(kPartThreads), stream, rgb, n_pixels, L.ppt,
                    L.tile, L.ntiles, keys16, info, status, err);
     if (hipGetLastError() != hipSuccess) return WSM_EHIP;
     WSM_LAUNCH(WSM_KERNEL_REDUCE_COMPACT, reduce_compact_kernel, dim3(kSlices),
