@@ -79,6 +79,20 @@ def test_reduce_edge_cases(shape, kind):
     assert np.array_equal(_u32(col), rc) and np.array_equal(_u32(cnt), rn)
 
 
+# Partition blocks are dealt tiles in XCD-contiguous runs (ntiles rounded up
+# to a multiple of 8, the blocks past the last tile idle): every tile count
+# mod 8, with 1024-pixel tiles, and one with 16384-pixel tiles.
+@pytest.mark.parametrize("n_pixels", [1024 * k + 5 for k in range(8, 16)] + [16384 * 515 - 7])
+def test_reduce_tile_counts_mod_8(n_pixels):
+    wsm = _wsm()
+    rng = np.random.default_rng(n_pixels)
+    img = (rng.integers(0, 64, size=(1, n_pixels, 3)) * 4 + 1).astype(np.uint8)
+    _say("reduce tile counts", n_pixels)
+    col, cnt = wsm.reduce_colors(_gpu_img(img))
+    rc, rn = oracle.reduce_colors(img)
+    assert np.array_equal(_u32(col), rc) and np.array_equal(_u32(cnt), rn)
+
+
 def test_reduce_unaligned_input_and_full_size():
     wsm = _wsm()
     img = synth.workload_image("large", 0)
