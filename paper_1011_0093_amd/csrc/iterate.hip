@@ -171,32 +171,36 @@ __global__ void init_state_kernel(StateView sv, int k, int points, int grid,
                                   const float *__restrict__ init_palette) {
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (gt == 0) {
-        Header *h = sv.hdr;
-        h->magic = kMagic;
-        h->k = k;
-        h->points = points;
-        h->grid = grid;
-        h->n_points = n_points;
-        h->n_pixels = n_pixels;
+    if (blockIdx.x == 0) {
+        // the palette's flags, its centers spread over the first block
         int flags = 0;
-        for (int c = 0; c < k; ++c)
+        for (int c = threadIdx.x; c < k; c += blockDim.x)
             flags |= center_flags(make_double4((double)init_palette[3 * c],
                                                (double)init_palette[3 * c + 1],
                                                (double)init_palette[3 * c + 2], 0.0));
-        h->wild = (flags & kFlagWild) ? 1 : 0;
-        h->pad = 0;
-        for (int j = 0; j < 3; ++j) h->reserved[j] = 0ull;
-        Record z;
-        z.iters = 0;
-        z.converged = 0;
-        z.err = 0;
-        z.mode = kModeResolve;
-        z.sse_last = 0.0;
-        z.pad2 = 0.0;
-        h->rec[0] = z;
-        h->rec[1] = z;
-        for (int j = 0; j < 4; ++j) h->info[j] = 0;
+        flags = __syncthreads_or(flags & kFlagWild);
+        if (threadIdx.x == 0) {
+            Header *h = sv.hdr;
+            h->magic = kMagic;
+            h->k = k;
+            h->points = points;
+            h->grid = grid;
+            h->n_points = n_points;
+            h->n_pixels = n_pixels;
+            h->wild = flags ? 1 : 0;
+            h->pad = 0;
+            for (int j = 0; j < 3; ++j) h->reserved[j] = 0ull;
+            Record z;
+            z.iters = 0;
+            z.converged = 0;
+            z.err = 0;
+            z.mode = kModeResolve;
+            z.sse_last = 0.0;
+            z.pad2 = 0.0;
+            h->rec[0] = z;
+            h->rec[1] = z;
+            for (int j = 0; j < 4; ++j) h->info[j] = 0;
+        }
     }
     for (int64_t c = gt; c < 2 * kMaxK; c += stride) {
         const int64_t j = c % kMaxK;  // both slots hold the initial palette
