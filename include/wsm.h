@@ -297,9 +297,12 @@ int wsm_iterate_graph_destroy(wsm_graph *graph);
  * hipExtLaunchKernelGGL and two HIP events, which the runtime records when
  * the kernel starts and when it ends, on the stream it is launched on;
  * wsm_timing_read waits for them and returns the first min(count, capacity)
- * durations in ms.  The hook
- * is process-wide and not thread-safe; attach creates 2 * capacity events
- * and detach destroys them.  Attaching while attached returns WSM_EINVAL. */
+ * durations in ms.  The hook is process-wide: its calls and the launches it
+ * claims events for take one lock, so they may come from several threads,
+ * but detach must not run while another thread launches the timed kernel
+ * (that launch may still be using the events it claimed).  Attach creates
+ * 2 * capacity events and detach destroys them.  Attaching while attached
+ * returns WSM_EINVAL. */
 typedef enum {
     WSM_KERNEL_REDUCE_PARTITION = 1,
     WSM_KERNEL_REDUCE_COMPACT = 2,

@@ -3,6 +3,8 @@
 // the runtime records when the kernel starts and ends, on the stream it is
 // launched on, so a caller can time that kernel's launches inside a larger
 // sequence without a profiler.  Not used on the normal path.
+#include <atomic>
+#include <mutex>
 #include <vector>
 
 #include "wsm_internal.h"
@@ -17,12 +19,16 @@ struct TimingState {
 };
 
 TimingState g_timing;
+std::mutex g_timing_mu;          // guards g_timing
+std::atomic<int> g_timed_kind{0};  // g_timing.which, read without the lock by every launch
 
 }  // namespace
 
 namespace wsm {
 
 bool timing_claim(int kind, hipEvent_t *begin, hipEvent_t *end) {
+    if (g_timed_kind.load(std::memory_order_acquire) != kind) return false;
+    std::lock_guard<std::mutex> lock(g_timing_mu);
     if (g_timing.which != kind || g_timing.count >= g_timing.capacity) return false;
     *begin = g_timing.begin[g_timing.count];
     *end = g_timing.end[g_timing.count];
@@ -36,6 +42,7 @@ extern "C" int wsm_timing_attach(int which, int capacity) {
     if (which < WSM_KERNEL_REDUCE_PARTITION || which > WSM_KERNEL_FULL_STEP || capacity < 1 ||
         capacity > (1 << 20))
         return WSM_EINVAL;
+    std::lock_guard<std::mutex> lock(g_timing_mu);
     if (g_timing.which != 0) return WSM_EINVAL;
     g_timing.begin.assign(capacity, nullptr);
     g_timing.end.assign(capacity, nullptr);
@@ -54,11 +61,13 @@ extern "C" int wsm_timing_attach(int which, int capacity) {
     g_timing.capacity = capacity;
     g_timing.count = 0;
     g_timing.which = which;
+    g_timed_kind.store(which, std::memory_order_release);
     return WSM_OK;
 }
 
 extern "C" int wsm_timing_read(float *ms, int capacity, int *count) {
     if (!count || (capacity > 0 && !ms)) return WSM_EINVAL;
+    std::lock_guard<std::mutex> lock(g_timing_mu);
     if (g_timing.which == 0) return WSM_EINVAL;
     const int n = g_timing.count < capacity ? g_timing.count : capacity;
     for (int i = 0; i < n; ++i) {
@@ -71,7 +80,9 @@ extern "C" int wsm_timing_read(float *ms, int capacity, int *count) {
 }
 
 extern "C" int wsm_timing_detach(void) {
+    std::lock_guard<std::mutex> lock(g_timing_mu);
     if (g_timing.which == 0) return WSM_OK;
+    g_timed_kind.store(0, std::memory_order_release);
     for (size_t i = 0; i < g_timing.begin.size(); ++i) {
         (void)hipEventSynchronize(g_timing.end[i]);
         (void)hipEventDestroy(g_timing.begin[i]);

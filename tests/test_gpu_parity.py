@@ -93,6 +93,35 @@ def test_reduce_tile_counts_mod_8(n_pixels):
     assert np.array_equal(_u32(col), rc) and np.array_equal(_u32(cnt), rn)
 
 
+def test_timing_hook_with_launches_from_several_threads():
+    """The measurement hook hands out its events under a lock: four threads,
+    each reducing on a stream of its own while the hook times the partition
+    kernel, get 12 distinct event pairs between them and bit-exact results."""
+    from concurrent.futures import ThreadPoolExecutor
+    wsm = _wsm()
+    img = synth.workload_image("small", 0)
+    rc, rn = oracle.reduce_colors(img)
+    g = _gpu_img(img)
+    _say("timing hook, 4 threads x 5 reductions of small seed 0")
+
+    def work(_):
+        torch.cuda.set_device(0)
+        st = torch.cuda.Stream()
+        ok = True
+        with torch.cuda.stream(st):
+            for _ in range(5):
+                col, cnt = wsm.reduce_colors(g)
+                ok &= np.array_equal(_u32(col), rc) and np.array_equal(_u32(cnt), rn)
+        st.synchronize()
+        return ok
+
+    with wsm.kernel_timer("reduce_partition", capacity=12) as kt:
+        with ThreadPoolExecutor(4) as ex:
+            oks = list(ex.map(work, range(4)))
+    assert all(oks)
+    assert len(kt.ms) == 12 and all(t > 0.0 for t in kt.ms)
+
+
 def test_reduce_unaligned_input_and_full_size():
     wsm = _wsm()
     img = synth.workload_image("large", 0)
