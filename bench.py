@@ -167,9 +167,10 @@ def main():
     k_streams = {K: torch.cuda.Stream(device=dev) for K in Ks}
     luts = {K: torch.empty(1 << 24, dtype=torch.uint8, device=dev) for K in Ks}
     # search blocks of each K while the three share the GPU (of 256 CUs): the
-    # longest chain (K = 256) keeps three quarters, K = 64 half, K = 16 a
-    # quarter (chosen by measurement; results do not depend on the grid)
-    share_grid = {16: 64, 64: 128, 256: 192}
+    # longest chain (K = 256) keeps three quarters, K = 64 and K = 16 half
+    # each; K = 16 is enqueued last and starts last, so it needs the blocks to
+    # catch up (chosen by measurement; results do not depend on the grid)
+    share_grid = {16: 128, 64: 128, 256: 192}
 
     def step(single_stream=args.single_stream):
         wsm.reduce_colors_into(img, colors, counts, nu, ws)
