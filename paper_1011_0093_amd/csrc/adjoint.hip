@@ -13,7 +13,8 @@
 // LDS; differences and sums are in float64 (the difference of two float32
 // values is exact in float64).  Per-block partials go to the workspace and
 // are summed in a fixed order by a second launch, so D is reproducible; the
-// palette gradient's per-block sums use LDS float64 atomics.
+// palette gradient's per-block sums use LDS float64 atomics, one per run of
+// equal centers within a wave (a segmented wave sum first).
 #include "sm_block.h"
 
 namespace wsm {
@@ -34,6 +35,37 @@ static AdjLayout adj_layout(int batch, int64_t n, int k) {
     L.off_c = align_up((size_t)batch * L.tiles * 8, 256);
     L.bytes = align_up(L.off_c + (size_t)batch * L.tiles * k * 3 * 8, 256);
     return L;
+}
+
+// Segmented inclusive sums of three float64 values over the wave (as
+// wave_seg_sum2 for two 64-bit integers): a segment starts at lanes with
+// head != 0, and the last lane of each segment ends with the segment's sums.
+template <int CTRL>
+__device__ __forceinline__ void seg_step_sum3_f64(int lane, int &f, double &a, double &b,
+                                                  double &c) {
+    const int tf = dpp_i32<CTRL>(f);
+    const double ta = dpp_f64<CTRL>(a);
+    const double tb = dpp_f64<CTRL>(b);
+    const double tc = dpp_f64<CTRL>(c);
+    if (dpp_takes<CTRL>(lane)) {
+        if (!f) {
+            a += ta;
+            b += tb;
+            c += tc;
+        }
+        f |= tf;
+    }
+}
+
+__device__ __forceinline__ void wave_seg_sum3_f64(int head, double &a, double &b, double &c) {
+    const int lane = threadIdx.x & 63;
+    int f = head;
+    seg_step_sum3_f64<kDppRowShr1>(lane, f, a, b, c);
+    seg_step_sum3_f64<kDppRowShr2>(lane, f, a, b, c);
+    seg_step_sum3_f64<kDppRowShr4>(lane, f, a, b, c);
+    seg_step_sum3_f64<kDppRowShr8>(lane, f, a, b, c);
+    seg_step_sum3_f64<kDppRowBcast15>(lane, f, a, b, c);
+    seg_step_sum3_f64<kDppRowBcast31>(lane, f, a, b, c);
 }
 
 __device__ __forceinline__ void load_palette(const float *__restrict__ pal, int k, float4 *cp) {
@@ -104,18 +136,26 @@ __global__ __launch_bounds__(kAdjThreads) void distortion_grad_kernel(
 #pragma unroll 4
     for (int j = 0; j < kAdjPpt; ++j) {
         const int64_t p = p0 + j * kAdjThreads + threadIdx.x;
-        if (p < n) {
-            const int m = mi[p];
+        const bool valid = p < n;
+        int m = -1;
+        double dx = 0.0, dy = 0.0, dz = 0.0;
+        if (valid) {
+            m = mi[p];
             const float4 c = cp[m];
-            const double dx = (double)xi[3 * p] - (double)c.x;
-            const double dy = (double)xi[3 * p + 1] - (double)c.y;
-            const double dz = (double)xi[3 * p + 2] - (double)c.z;
+            dx = (double)xi[3 * p] - (double)c.x;
+            dy = (double)xi[3 * p + 1] - (double)c.y;
+            dz = (double)xi[3 * p + 2] - (double)c.z;
             if (gxi) {
                 gxi[3 * p] = (float)(scale * dx);
                 gxi[3 * p + 1] = (float)(scale * dy);
                 gxi[3 * p + 2] = (float)(scale * dz);
             }
-            if (part) {
+        }
+        if (part) {  // uniform: every lane of the wave takes part
+            // Neighbouring pixels mostly share a center: the wave sums each
+            // run of equal centers first, and the run's last lane adds it.
+            wave_seg_sum3_f64(run_head(m), dx, dy, dz);
+            if (run_tail(m, valid)) {
                 atomicAdd(&acc[3 * m], dx);
                 atomicAdd(&acc[3 * m + 1], dy);
                 atomicAdd(&acc[3 * m + 2], dz);
