@@ -76,6 +76,20 @@ __device__ __forceinline__ void load_palette(const float *__restrict__ pal, int 
 
 // Block b of image i: sum over its pixels of ||x_p - c_m(p)||^2 (float64),
 // reduced in a fixed order (lanes, then waves), into part[i][b].
+// Four consecutive pixels from a lane's 16-byte-aligned base q: their 12
+// float32 colors (three 16-byte loads) and their 4 palette indices (one
+// 4-byte load).  VEC launches need n % 4 == 0 and 16-byte aligned x.
+__device__ __forceinline__ void load_quad(const float *xi, const uint8_t *mi, int64_t q,
+                                          float (&xv)[12], uint32_t &m4) {
+    const float4 *src = (const float4 *)(xi + 3 * q);
+    const float4 a = src[0], b = src[1], c = src[2];
+    const float v[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int e = 0; e < 12; ++e) xv[e] = v[e];
+    m4 = *(const uint32_t *)(mi + q);
+}
+
+template <bool VEC>
 __global__ __launch_bounds__(kAdjThreads) void distortion_partial_kernel(
     const float *__restrict__ x, const uint8_t *__restrict__ idx, const float *__restrict__ pal,
     int64_t n, int k, int64_t tiles, double *__restrict__ part) {
@@ -88,15 +102,35 @@ __global__ __launch_bounds__(kAdjThreads) void distortion_partial_kernel(
     const uint8_t *mi = idx + img * n;
     const int64_t p0 = (int64_t)blockIdx.x * kAdjTile;
     double s = 0.0;
+    if (VEC) {
+#pragma unroll 2
+        for (int it = 0; it < kAdjPpt / 4; ++it) {
+            const int64_t q = p0 + ((int64_t)it * kAdjThreads + threadIdx.x) * 4;
+            if (q < n) {  // n % 4 == 0: all four pixels are in the image
+                float xv[12];
+                uint32_t m4;
+                load_quad(xi, mi, q, xv, m4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float4 c = cp[(m4 >> (8 * e)) & 0xFFu];
+                    const double dx = (double)xv[3 * e] - (double)c.x;
+                    const double dy = (double)xv[3 * e + 1] - (double)c.y;
+                    const double dz = (double)xv[3 * e + 2] - (double)c.z;
+                    s += dx * dx + dy * dy + dz * dz;
+                }
+            }
+        }
+    } else {
 #pragma unroll 4
-    for (int j = 0; j < kAdjPpt; ++j) {
-        const int64_t p = p0 + j * kAdjThreads + threadIdx.x;
-        if (p < n) {
-            const float4 c = cp[mi[p]];
-            const double dx = (double)xi[3 * p] - (double)c.x;
-            const double dy = (double)xi[3 * p + 1] - (double)c.y;
-            const double dz = (double)xi[3 * p + 2] - (double)c.z;
-            s += dx * dx + dy * dy + dz * dz;
+        for (int j = 0; j < kAdjPpt; ++j) {
+            const int64_t p = p0 + j * kAdjThreads + threadIdx.x;
+            if (p < n) {
+                const float4 c = cp[mi[p]];
+                const double dx = (double)xi[3 * p] - (double)c.x;
+                const double dy = (double)xi[3 * p + 1] - (double)c.y;
+                const double dz = (double)xi[3 * p + 2] - (double)c.z;
+                s += dx * dx + dy * dy + dz * dz;
+            }
         }
     }
     const double t = block_sum_f64<kAdjThreads>(s, scr);
@@ -117,6 +151,7 @@ __global__ __launch_bounds__(64) void distortion_reduce_kernel(const double *__r
 // Adjoint, block b of image i: dD/dx for its pixels (when grad_x is not
 // null) and the sums over its pixels of x_p - c_m(p) per center, into
 // part[i][b][k][3] (when the palette gradient is wanted).
+template <bool VEC>
 __global__ __launch_bounds__(kAdjThreads) void distortion_grad_kernel(
     const float *__restrict__ x, const uint8_t *__restrict__ idx, const float *__restrict__ pal,
     int64_t n, int k, int64_t tiles, const double *__restrict__ grad_d, float *__restrict__ grad_x,
@@ -133,6 +168,47 @@ __global__ __launch_bounds__(kAdjThreads) void distortion_grad_kernel(
     const uint8_t *mi = idx + img * n;
     float *gxi = grad_x ? grad_x + img * n * 3 : nullptr;
     const int64_t p0 = (int64_t)blockIdx.x * kAdjTile;
+    if (VEC) {
+        for (int it = 0; it < kAdjPpt / 4; ++it) {
+            const int64_t q = p0 + ((int64_t)it * kAdjThreads + threadIdx.x) * 4;
+            const bool valid = q < n;  // n % 4 == 0: all four pixels or none
+            float xv[12] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            uint32_t m4 = 0u;
+            if (valid) load_quad(xi, mi, q, xv, m4);
+            double d[12];
+            int m[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                m[e] = valid ? (int)((m4 >> (8 * e)) & 0xFFu) : -1;
+                const float4 c = valid ? cp[m[e]] : make_float4(0.f, 0.f, 0.f, 0.f);
+                d[3 * e] = valid ? (double)xv[3 * e] - (double)c.x : 0.0;
+                d[3 * e + 1] = valid ? (double)xv[3 * e + 1] - (double)c.y : 0.0;
+                d[3 * e + 2] = valid ? (double)xv[3 * e + 2] - (double)c.z : 0.0;
+            }
+            if (gxi && valid) {
+                float g[12];
+#pragma unroll
+                for (int e = 0; e < 12; ++e) g[e] = (float)(scale * d[e]);
+                float4 *dst = (float4 *)(gxi + 3 * q);
+                dst[0] = make_float4(g[0], g[1], g[2], g[3]);
+                dst[1] = make_float4(g[4], g[5], g[6], g[7]);
+                dst[2] = make_float4(g[8], g[9], g[10], g[11]);
+            }
+            if (part) {  // uniform: every lane of the wave takes part
+                // pixel e of every lane in turn: neighbouring lanes' pixels
+                // are 4 apart and mostly share a center as well
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    wave_seg_sum3_f64(run_head(m[e]), d[3 * e], d[3 * e + 1], d[3 * e + 2]);
+                    if (run_tail(m[e], valid)) {
+                        atomicAdd(&acc[3 * m[e]], d[3 * e]);
+                        atomicAdd(&acc[3 * m[e] + 1], d[3 * e + 1]);
+                        atomicAdd(&acc[3 * m[e] + 2], d[3 * e + 2]);
+                    }
+                }
+            }
+        }
+    } else {
 #pragma unroll 4
     for (int j = 0; j < kAdjPpt; ++j) {
         const int64_t p = p0 + j * kAdjThreads + threadIdx.x;
@@ -161,6 +237,7 @@ __global__ __launch_bounds__(kAdjThreads) void distortion_grad_kernel(
                 atomicAdd(&acc[3 * m + 2], dz);
             }
         }
+    }
     }
     if (part) {
         __syncthreads();
@@ -222,6 +299,14 @@ static int adj_check(const float *x, const uint8_t *index, const float *palette,
     return WSM_OK;
 }
 
+// Whether the kernels take four pixels per lane with 16-byte accesses:
+// every image's colors (and gradients) 16-byte aligned and its indices
+// 4-byte aligned.
+static bool adj_vec(const float *x, const uint8_t *index, const float *grad_x, int64_t n) {
+    return n % 4 == 0 && ((uintptr_t)x & 15u) == 0u && ((uintptr_t)index & 3u) == 0u &&
+           (!grad_x || ((uintptr_t)grad_x & 15u) == 0u);
+}
+
 extern "C" int wsm_distortion_workspace_bytes(int batch, int64_t n_pixels, int k, size_t *bytes) {
     if (!bytes || batch < 1 || batch > 65535 || n_pixels < 1 || n_pixels > (int64_t)0xFFFFFFFFll ||
         k < 1 || k > kMaxK)
@@ -239,8 +324,16 @@ extern "C" int wsm_distortion(const float *x, const uint8_t *index, const float 
     const AdjLayout L = adj_layout(batch, n_pixels, k);
     double *part = (double *)((char *)workspace + L.off_d);
     (void)hipGetLastError();
-    distortion_partial_kernel<<<dim3((unsigned)L.tiles, (unsigned)batch), dim3(kAdjThreads), 0,
-                                stream>>>(x, index, palette, n_pixels, k, L.tiles, part);
+    if (adj_vec(x, index, nullptr, n_pixels))
+        distortion_partial_kernel<true><<<dim3((unsigned)L.tiles, (unsigned)batch),
+                                          dim3(kAdjThreads), 0, stream>>>(x, index, palette,
+                                                                          n_pixels, k, L.tiles,
+                                                                          part);
+    else
+        distortion_partial_kernel<false><<<dim3((unsigned)L.tiles, (unsigned)batch),
+                                           dim3(kAdjThreads), 0, stream>>>(x, index, palette,
+                                                                           n_pixels, k, L.tiles,
+                                                                           part);
     distortion_reduce_kernel<<<dim3((unsigned)batch), dim3(64), 0, stream>>>(part, L.tiles,
                                                                             n_pixels, d_out);
     return hipGetLastError() == hipSuccess ? WSM_OK : WSM_EHIP;
@@ -260,9 +353,14 @@ extern "C" int wsm_distortion_backward(const float *x, const uint8_t *index, con
     const AdjLayout L = adj_layout(batch, n_pixels, k);
     double *part = grad_palette ? (double *)((char *)workspace + L.off_c) : nullptr;
     (void)hipGetLastError();
-    distortion_grad_kernel<<<dim3((unsigned)L.tiles, (unsigned)batch), dim3(kAdjThreads), 0,
-                             stream>>>(x, index, palette, n_pixels, k, L.tiles, grad_d, grad_x,
-                                       part);
+    if (adj_vec(x, index, grad_x, n_pixels))
+        distortion_grad_kernel<true><<<dim3((unsigned)L.tiles, (unsigned)batch),
+                                       dim3(kAdjThreads), 0, stream>>>(
+            x, index, palette, n_pixels, k, L.tiles, grad_d, grad_x, part);
+    else
+        distortion_grad_kernel<false><<<dim3((unsigned)L.tiles, (unsigned)batch),
+                                        dim3(kAdjThreads), 0, stream>>>(
+            x, index, palette, n_pixels, k, L.tiles, grad_d, grad_x, part);
     if (grad_palette)
         grad_palette_reduce_kernel<<<dim3((unsigned)((k * 3 + 63) / 64), (unsigned)batch),
                                      dim3(kAdjThreads), 0, stream>>>(part, L.tiles, n_pixels, k,

@@ -78,6 +78,40 @@ def test_distortion_and_gradients_equal_the_oracle(shift):
         assert (np.abs(gc[b] - gc_ref) <= tol).all(), np.abs(gc[b] - gc_ref).max()
 
 
+@pytest.mark.parametrize("shape,offset", [((255, 257), 0), ((128, 128), 1), ((128, 128), 0)])
+def test_both_kernel_paths_against_the_oracle(shape, offset):
+    """The adjoint kernels take four pixels per lane with 16-byte accesses
+    when the pixel count is a multiple of 4 and the buffers are aligned, one
+    pixel per lane otherwise: an odd pixel count (255 x 257), colors that
+    start 4 bytes into their buffer, and the aligned case, each against the
+    oracle's float64 D and gradients."""
+    wsm = _wsm()
+    h, w = shape
+    _say("adjoint kernel paths, 2 images", shape, "float offset", offset)
+    x_np = np.stack([synth.sinusoid_field_image(s, h, w) for s in (4, 5)]).astype(np.float32)
+    x, pal, idx, _ = _forward(x_np, 16, 10, 0.0)
+    B, n = 2, h * w
+    buf = torch.empty(B * n * 3 + offset, dtype=torch.float32, device="cuda")
+    buf[offset:] = x.reshape(-1)
+    xf = buf[offset:].view(B, n, 3)
+    d = torch.empty(B, dtype=torch.float64, device="cuda")
+    g = torch.tensor([1.0, -0.5], dtype=torch.float64, device="cuda")
+    gx = torch.empty(B, n, 3, dtype=torch.float32, device="cuda")
+    gc = torch.empty_like(pal)
+    ws = wsm.distortion_workspace(B, n, 16, xf.device)
+    wsm.distortion_into(xf, pal, idx, d, ws, g, gx, gc)
+    d, gx, gc = d.cpu().numpy(), gx.cpu().numpy(), gc.cpu().numpy()
+    pal_np = pal.cpu().numpy().astype(np.float64)
+    idx_np = idx.cpu().numpy()
+    for b in range(B):
+        xb = x_np[b].reshape(-1, 3).astype(np.float64)
+        assert d[b] == pytest.approx(oracle.distortion(xb, idx_np[b], pal_np[b]), rel=SUM_RTOL)
+        gx_ref, gc_ref = oracle.distortion_grad(xb, idx_np[b], pal_np[b], [1.0, -0.5][b])
+        np.testing.assert_allclose(gx[b], gx_ref, rtol=2 ** -23, atol=1e-30)
+        tol = 2 ** -23 * np.abs(gc_ref) + 1e-12 * np.abs(gx_ref).sum()
+        assert (np.abs(gc[b] - gc_ref) <= tol).all(), np.abs(gc[b] - gc_ref).max()
+
+
 def _true_distortion_colors(colors, counts, n_pix, centers, m):
     """The true D (every color at its nearest center under the map's key)
     over the unique colors, and the assignment."""
