@@ -47,16 +47,16 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/search_kernel_512x512_traffic.md).  It describes the kernel
 # sources it was measured on (hash below); for any other sources the bench
 # reports null.
-SEARCH_TRAFFIC_BYTES = 3846983
+SEARCH_TRAFFIC_BYTES = 3846919
 SEARCH_TRAFFIC_SRC = "7cec0f1246baf378"
 _KERNEL_SOURCES = ("iterate.hip", "iter_device.h", "sm_block.h", "wave_ops.h", "wsm_internal.h")
 
 # The same for the 4096x4096 reduction (partition + compaction, bytes per
 # call) and pixel gather (bytes per launch)
 # (profiles/reduce_map_4096x4096_traffic.md).
-REDUCE_TRAFFIC_BYTES = 173731463
+REDUCE_TRAFFIC_BYTES = 173722701
 REDUCE_TRAFFIC_SRC = "3daaa189cbeb9d45"
-GATHER_TRAFFIC_BYTES = 106378170
+GATHER_TRAFFIC_BYTES = 106355179
 GATHER_TRAFFIC_SRC = "152d475eeb197d94"
 _REDUCE_SOURCES = ("reduce.hip", "wave_ops.h", "wsm_internal.h")
 _MAP_SOURCES = ("map.hip", "sm_block.h", "wave_ops.h", "wsm_internal.h")
